@@ -1,0 +1,226 @@
+/*
+ * libharp: reduced Macro-Basis-Function array solver with the HARP interaction
+ * model (Bui-Van et al., "Fast and Accurate Simulation Technique for Large
+ * Irregular Arrays", arXiv 1702.03781), for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every pointer named d_* is device memory owned by the caller; every
+ * other pointer is host memory owned by the caller.  The library never
+ * allocates device memory: calls that need scratch space take a workspace
+ * (d_ws, ws_bytes) whose size a *_ws query returns.  All device work is
+ * enqueued on the caller's stream and is asynchronous, except where a call
+ * says it synchronises.  Argument errors are returned synchronously and
+ * nothing is enqueued; numerical outcomes (domain counts, zero pivots,
+ * refinement reports) are written to device arrays or, after a documented
+ * synchronisation, to host reports.  Nothing throws across this interface.
+ *
+ * Matrices are column-major with interleaved complex storage (re, im), as
+ * complex64 (HARP_C64) or complex128 (HARP_C128); "ld" is the leading
+ * dimension in complex elements and "stride" the distance in complex elements
+ * between consecutive matrices of a batch.
+ *
+ * Indexing of the reduced matrix (Section II-A): antenna m carries MBFs
+ * T = 0..N_m-1; unknown (m, T) is row/column m * N_m + T.  Entry
+ * Z[(m,T),(n,S)] is the reaction of testing MBF T on antenna m with source
+ * MBF S on antenna n.
+ */
+#ifndef HARP_H
+#define HARP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HARP_OK = 0,
+    HARP_E_ARG = -1,       /* invalid argument (size, pointer, layout, NaN input) */
+    HARP_E_DOMAIN = -2,    /* a pair closer than the model's inner radius r_min */
+    HARP_E_SINGULAR = -3,  /* exact zero pivot in the factorisation */
+    HARP_E_NOCONV = -4,    /* refinement did not reach its tolerance */
+    HARP_E_HIP = -5,       /* a HIP runtime call failed */
+    HARP_E_WORKSPACE = -6  /* workspace missing or smaller than the *_ws query */
+} harp_status;
+
+typedef enum { HARP_C64 = 0, HARP_C128 = 1 } harp_dtype;
+
+const char *harp_status_str(harp_status s);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t harp_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Element description                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* One antenna type: n_mbf macro basis functions (the "primary and
+ * secondaries" MBFs of Section II), each represented by n_samp point-dipole
+ * samples.  d_samples is device memory, [n_mbf][n_samp][8] float64 records
+ * (x, y, z, ux, uy, uz, a_re, a_im): position in metres relative to the
+ * element reference point (which sits at (x_m, y_m, 0) in the array), unit
+ * orientation, complex moment in A m.  wire_radius (m) regularises the
+ * zero-distance (self) interaction.  The port of the element drives its MBFs
+ * with weights w_T = moment of sample 0 of MBF T. */
+typedef struct {
+    int32_t n_mbf;
+    int32_t n_samp;
+    const double *d_samples;
+    double wire_radius;
+} harp_element;
+
+/* ------------------------------------------------------------------------ */
+/* HARP model (Section II-A/B, Eqs. 1-4)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* A model is one device blob per element and frequency.  Layout (all offsets
+ * in bytes from the blob start, each section 256-byte aligned):
+ *   [0, 256)    header: uint32 magic 0x50524148, uint32 version 1,
+ *               int32 n_mbf, n_samp, P, Q, n_alpha, n_t,
+ *               float64 freq_hz, k, omega_mu, r_min, wire_radius,
+ *               int64 off_coef, off_coef32, off_self, off_port, off_samples,
+ *               total_bytes; zero padding.
+ *   off_coef    complex128 C[T][S][p+P][q], p = -P..P, q = 0..Q
+ *   off_coef32  complex64 rounding of C (read by the complex64 fill)
+ *   off_self    complex128 Z_self[T][S] (zero-distance block)
+ *   off_port    complex128 w[T]
+ *   off_samples float64 [n_mbf][n_samp][8] copy of the element samples
+ * The model evaluates, for a testing antenna at relative position
+ * R = r (cos a, sin a) from the source antenna, t = r_min / r:
+ *   Z_TS(r, a) = e^{-jkr} sum_{p=-P..P} e^{j p a} sum_{q=0..Q} C_pq t^q
+ * which is Eq. (4) with the far-field term of Eq. (1) expanded on the same
+ * Fourier basis and folded into q = 1 (1/r = t / r_min). */
+size_t harp_model_bytes(int32_t n_mbf, int32_t n_samp, int32_t P, int32_t Q);
+
+harp_status harp_fit_ws(int32_t n_mbf, int32_t n_samp, int32_t P, int32_t Q, int32_t n_alpha,
+                        int32_t n_t, size_t *bytes);
+
+/* Build the model of `elem` at freq_hz (Section II-A, Eqs. 1-3, with the
+ * Section II-B improvements): exact FP64 reactions on the polar grid
+ * a_i = 2 pi i / n_alpha, t_l = l / n_t (l = 1..n_t, r_l = r_min / t_l), the
+ * remainder of Eq. (2) after the far field of Eq. (1), a DFT over a for
+ * |p| <= P and a Householder least-squares fit over t (including B = 0 at
+ * t = 0) for q = 0..Q; plus the zero-distance block with the thin-wire
+ * reduced kernel and the port weights.
+ * Requirements: n_alpha >= 2P + 1 and even, n_t >= Q, r_min > 0,
+ * model_bytes >= harp_model_bytes(...), ws_bytes >= harp_fit_ws(...).
+ * Asynchronous on `stream`. */
+harp_status harp_fit(const harp_element *elem, double freq_hz, int32_t P, int32_t Q, double r_min,
+                     int32_t n_alpha, int32_t n_t, void *d_model, size_t model_bytes, void *d_ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Reduced-matrix fill (Eq. 4)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Fill n_freq reduced matrices of order n = n_ant * n_mbf from n_freq models
+ * stored model_stride bytes apart in d_models (all with the given n_mbf and
+ * polynomial order Q, harmonic order P <= p_max).  For every ordered pair of
+ * antennas m != n the N_m x N_m block is the model at R = (x_m - x_n,
+ * y_m - y_n); diagonal blocks are Z_self; when ri > 0, blocks with r > ri
+ * are zero (radius of influence, Section II-D).
+ *   dtype HARP_C128: FP64 evaluation, d_Z complex128.
+ *   dtype HARP_C64 : FP32 evaluation (distance and k r reduced in FP64),
+ *                    d_Z complex64.
+ *   d_Z32 != NULL (only with HARP_C128): the FP64 result is also written
+ *                    rounded to complex64 into d_Z32 (ld32, stride32).
+ * d_info[f] (int32, device) receives the number of ordered pairs with
+ * r < r_min (outside the model; their blocks hold the polynomial continued
+ * beyond t = 1), or -1 if model f does not match n_mbf / Q / p_max.
+ * Positions d_x, d_y: float64 [n_ant], metres. Asynchronous. */
+harp_status harp_fill(const void *d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
+                      int32_t Q, int32_t p_max, const double *d_x, const double *d_y,
+                      int32_t n_ant, double ri, harp_dtype dtype, void *d_Z, int64_t ldz,
+                      int64_t stride_z, void *d_Z32, int64_t ld32, int64_t stride32,
+                      int32_t *d_info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Ports (Sections I and II-C)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Unit-voltage excitation of every port: B = I_{n_ant} (x) w, complex128
+ * n x n_ant per frequency (column j holds w on the rows of antenna j). */
+harp_status harp_port_rhs(const void *d_models, int64_t model_stride, int32_t n_freq,
+                          int32_t n_mbf, int32_t n_ant, void *d_B, int64_t ldb, int64_t stride_b,
+                          hipStream_t stream);
+
+/* Port admittances Y = W^T X (complex128, n_ant x n_ant per frequency):
+ * Y_ij is the current at port i for a unit voltage at port j. */
+harp_status harp_port_admittance(const void *d_models, int64_t model_stride, int32_t n_freq,
+                                 int32_t n_mbf, int32_t n_ant, const void *d_X, int64_t ldx,
+                                 int64_t stride_x, void *d_Y, int64_t ldy, int64_t stride_y,
+                                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Dense reduced solve (Section I: Gaussian elimination, one RHS per port)   */
+/* ------------------------------------------------------------------------ */
+
+harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t *bytes);
+
+/* In-place LU factorisation with partial pivoting of `batch` n x n matrices
+ * (complex64 or complex128, lda >= n): blocked right-looking elimination,
+ * pivot = first row maximising |Re| + |Im| in the column.  On return the
+ * upper triangle holds U and the strict lower triangle the multipliers of L;
+ * d_ipiv[b * n + i] (int32, device) is the row exchanged with row i at step
+ * i.  Row exchanges found in a later column block are not applied to the
+ * multipliers of earlier blocks: the factors are meant for reduced_solve.
+ * d_info[b] = 0, or i + 1 if U(i, i) is exactly zero (the factorisation then
+ * continues; a solve with it is meaningless).  Asynchronous. */
+harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void *d_A, int64_t lda,
+                           int64_t stride_a, int32_t *d_ipiv, int32_t *d_info, void *d_ws,
+                           size_t ws_bytes, hipStream_t stream);
+
+/* FP64 iterative refinement of a solve whose factors are complex64. */
+typedef struct {
+    const void *d_Z;     /* complex128 matrices the residual is taken against */
+    int64_t ldz;
+    int64_t stride_z;
+    double tol;          /* stop when ||B - Z X||_F <= tol ||Z||_F ||X||_F */
+    int32_t max_iter;    /* maximum number of correction sweeps (>= 0) */
+} harp_refine;
+
+typedef struct {
+    int32_t iters;       /* correction sweeps applied */
+    int32_t converged;   /* 1 if the tolerance was met */
+    double resid_rel;    /* last ||B - Z X||_F / (||Z||_F ||X||_F) */
+} harp_refine_report;
+
+harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
+                             int32_t refine, size_t *bytes);
+
+/* Solve A X = B for `batch` systems with the factors of reduced_factor
+ * (dtype as factored).  B and X are complex128 (n x nrhs).  With refine ==
+ * NULL, X is the solve in the factor precision.  With refine != NULL: the
+ * residual R = B - Z X is formed in FP64 against refine->d_Z, corrections
+ * are solved with the factors and added in FP64, until the tolerance or
+ * max_iter; this path synchronises the stream once per sweep, and, if
+ * report != NULL (host, [batch]), fills it.  Returns HARP_E_NOCONV if a
+ * system missed the tolerance. */
+harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
+                          const void *d_LU, int64_t lda, int64_t stride_lu, const int32_t *d_ipiv,
+                          const void *d_B, int64_t ldb, int64_t stride_b, void *d_X, int64_t ldx,
+                          int64_t stride_x, const harp_refine *refine,
+                          harp_refine_report *report, void *d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Embedded element patterns (Eqs. 5-6)                                      */
+/* ------------------------------------------------------------------------ */
+
+/* For each of n_ports coefficient columns of d_X (complex128, n x n_ports,
+ * ld ldx) and each direction (theta, phi) (float64 radians, device):
+ *   E = -(j omega mu0 / 4 pi) sum_T F_T(u) sum_i X[i N_m + T] e^{jk(u_x x_i + u_y y_i)}
+ * projected on theta-hat and phi-hat, with F_T the radiation vector of MBF T
+ * (sum over its samples of a s_perp e^{+jk u . rho}).  d_E: complex128
+ * [n_ports][n_dir][2].  Asynchronous. */
+harp_status embedded_patterns(const void *d_model, int32_t n_mbf, const double *d_x,
+                              const double *d_y, int32_t n_ant, const void *d_X, int64_t ldx,
+                              int32_t n_ports, const double *d_theta, const double *d_phi,
+                              int32_t n_dir, void *d_E, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARP_H */

@@ -1,0 +1,350 @@
+"""Python binding of libharp: argument marshalling only.
+
+Every numerical step runs in the HIP library; PyTorch provides device memory
+and the current stream.  Function names follow the C ABI (include/harp.h).
+
+Matrices are returned as column-major views: a batch of n x m matrices is a
+tensor ``M`` of shape (batch, n, m) with ``M.stride() == (s, 1, ld)``, which
+is what the library reads and writes (ld = leading dimension).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import struct
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from ._lib import HarpElement, HarpRefine, HarpRefineReport, check, lib
+
+C64, C128 = 0, 1
+_DT = {"c64": C64, "c128": C128, torch.complex64: C64, torch.complex128: C128}
+_TORCH_DT = {C64: torch.complex64, C128: torch.complex128}
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def colmajor(batch: int, rows: int, cols: int, dtype, device) -> torch.Tensor:
+    """Allocate a batch of column-major matrices (ld = rows)."""
+    return torch.empty((batch, cols, rows), dtype=dtype, device=device).transpose(1, 2)
+
+
+def _cm(M: torch.Tensor, name: str):
+    """(ptr, ld, stride) of a batched column-major tensor (batch, rows, cols)."""
+    if M.dim() == 2:
+        M = M.unsqueeze(0)
+    if M.dim() != 3 or not M.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA tensor (batch, rows, cols)")
+    b, r, c = M.shape
+    if M.stride(1) != 1 and r > 1:
+        raise ValueError(f"{name}: not column-major (stride {M.stride()})")
+    ld = M.stride(2) if c > 1 else r
+    if ld < r:
+        raise ValueError(f"{name}: leading dimension {ld} < rows {r}")
+    stride = M.stride(0) if b > 1 else ld * c
+    return _ptr(M), ld, stride
+
+
+# --------------------------------------------------------------------------
+# models
+# --------------------------------------------------------------------------
+
+_HDR = struct.Struct("<II6i5d6q")
+
+
+@dataclass
+class Model:
+    """One HARP model (one element type at one frequency) in device memory."""
+    blob: torch.Tensor      # uint8, device
+    n_mbf: int
+    n_samp: int
+    P: int
+    Q: int
+    freq: float
+    r_min: float
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.blob.numel())
+
+
+def model_bytes(n_mbf: int, n_samp: int, P: int, Q: int) -> int:
+    return int(lib().harp_model_bytes(n_mbf, n_samp, P, Q))
+
+
+def harp_fit(samples: torch.Tensor, wire_radius: float, freq: float, P: int, Q: int,
+             r_min: float, n_alpha: int | None = None, n_t: int | None = None) -> Model:
+    """Build the model of an element (device samples [n_mbf, n_samp, 8] f64)."""
+    if samples.dtype != torch.float64 or not samples.is_cuda or samples.dim() != 3:
+        raise ValueError("samples: CUDA float64 tensor [n_mbf, n_samp, 8]")
+    samples = samples.contiguous()
+    n_mbf, n_samp = samples.shape[0], samples.shape[1]
+    n_alpha = 4 * (P + 1) if n_alpha is None else n_alpha
+    n_t = 2 * (Q + 1) if n_t is None else n_t
+    nb = model_bytes(n_mbf, n_samp, P, Q)
+    blob = torch.zeros(nb, dtype=torch.uint8, device=samples.device)
+    ws_b = ctypes.c_size_t()
+    check(lib().harp_fit_ws(n_mbf, n_samp, P, Q, n_alpha, n_t, ctypes.byref(ws_b)), "harp_fit_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=samples.device)
+    el = HarpElement(n_mbf, n_samp, _ptr(samples), float(wire_radius))
+    check(lib().harp_fit(ctypes.byref(el), float(freq), P, Q, float(r_min), n_alpha, n_t,
+                         _ptr(blob), nb, _ptr(ws), ws_b.value, _stream(samples.device)),
+          "harp_fit")
+    blob._keep = (samples, ws)  # keep inputs alive until the stream has consumed them
+    return Model(blob, n_mbf, n_samp, P, Q, float(freq), float(r_min))
+
+
+def pack_model(C: np.ndarray, Z_self: np.ndarray, w: np.ndarray, samples: np.ndarray,
+               freq: float, k: float, omega_mu: float, r_min: float, wire_radius: float,
+               device="cuda") -> Model:
+    """Write a model blob (layout of include/harp.h) from host arrays, e.g. a
+    table produced by another fitter or loaded from disk."""
+    n_mbf, _, np2, q1 = C.shape
+    P, Q = (np2 - 1) // 2, q1 - 1
+    n_samp = samples.shape[1]
+    total = model_bytes(n_mbf, n_samp, P, Q)
+
+    def a256(b):
+        return (b + 255) & ~255
+
+    ncoef = n_mbf * n_mbf * np2 * q1
+    off_coef = 256
+    off_coef32 = off_coef + a256(ncoef * 16)
+    off_self = off_coef32 + a256(ncoef * 8)
+    off_port = off_self + a256(n_mbf * n_mbf * 16)
+    off_samples = off_port + a256(n_mbf * 16)
+    buf = np.zeros(total, dtype=np.uint8)
+    hdr = _HDR.pack(0x50524148, 1, n_mbf, n_samp, P, Q, 0, 0, freq, k, omega_mu, r_min,
+                    wire_radius, off_coef, off_coef32, off_self, off_port, off_samples, total)
+    buf[:len(hdr)] = np.frombuffer(hdr, dtype=np.uint8)
+
+    def put(off, arr):
+        b = np.ascontiguousarray(arr).view(np.uint8).ravel()
+        buf[off:off + b.size] = b
+
+    put(off_coef, C.astype(np.complex128))
+    put(off_coef32, C.astype(np.complex64))
+    put(off_self, Z_self.astype(np.complex128))
+    put(off_port, w.astype(np.complex128))
+    put(off_samples, samples.astype(np.float64))
+    blob = torch.from_numpy(buf).to(device)
+    return Model(blob, n_mbf, n_samp, P, Q, float(freq), float(r_min))
+
+
+@dataclass
+class ModelBatch:
+    """Models of one element type at several frequencies, equal stride."""
+    data: torch.Tensor      # uint8 [n_freq, stride]
+    n_mbf: int
+    Q: int
+    p_max: int
+    freqs: list
+
+    @property
+    def n_freq(self) -> int:
+        return int(self.data.shape[0])
+
+    @property
+    def stride(self) -> int:
+        return int(self.data.shape[1])
+
+
+def stack_models(models) -> ModelBatch:
+    n_mbf = {m.n_mbf for m in models}
+    Q = {m.Q for m in models}
+    if len(n_mbf) != 1 or len(Q) != 1:
+        raise ValueError("stack_models: models must share n_mbf and Q")
+    stride = max(m.nbytes for m in models)
+    stride = (stride + 255) & ~255
+    data = torch.zeros((len(models), stride), dtype=torch.uint8, device=models[0].blob.device)
+    for i, m in enumerate(models):
+        data[i, :m.nbytes] = m.blob
+    return ModelBatch(data, n_mbf.pop(), Q.pop(), max(m.P for m in models),
+                      [m.freq for m in models])
+
+
+def read_model_header(model: Model) -> dict:
+    vals = _HDR.unpack(bytes(model.blob[:_HDR.size].cpu().numpy()))
+    keys = ["magic", "version", "n_mbf", "n_samp", "P", "Q", "n_alpha", "n_t", "freq_hz", "k",
+            "omega_mu", "r_min", "wire_radius", "off_coef", "off_coef32", "off_self", "off_port",
+            "off_samples", "total_bytes"]
+    return dict(zip(keys, vals))
+
+
+def model_arrays(model: Model) -> dict:
+    """Host copies of the sections of a model blob (C, Z_self, w)."""
+    h = read_model_header(model)
+    raw = model.blob.cpu().numpy()
+    nm, P, Q = h["n_mbf"], h["P"], h["Q"]
+    nc = nm * nm * (2 * P + 1) * (Q + 1)
+
+    def get(off, n, dt):
+        return raw[off:off + n * np.dtype(dt).itemsize].view(dt)
+
+    return {
+        "C": get(h["off_coef"], nc, np.complex128).reshape(nm, nm, 2 * P + 1, Q + 1),
+        "C32": get(h["off_coef32"], nc, np.complex64).reshape(nm, nm, 2 * P + 1, Q + 1),
+        "Z_self": get(h["off_self"], nm * nm, np.complex128).reshape(nm, nm),
+        "w": get(h["off_port"], nm, np.complex128),
+        "header": h,
+    }
+
+
+# --------------------------------------------------------------------------
+# fill, ports
+# --------------------------------------------------------------------------
+
+def harp_fill(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, dtype="c64", ri: float = 0.0,
+              Z: torch.Tensor | None = None, Z32: torch.Tensor | None = None,
+              dual: bool = False):
+    """Fill the reduced matrices of all frequencies (Eq. 4).  Returns (Z, Z32,
+    info); Z32 is the complex64 copy when dual=True (dtype must be c128)."""
+    dt = _DT[dtype]
+    dev = models.data.device
+    n_ant = int(x.numel())
+    n = n_ant * models.n_mbf
+    if Z is None:
+        Z = colmajor(models.n_freq, n, n, _TORCH_DT[dt], dev)
+    if dual and Z32 is None:
+        Z32 = colmajor(models.n_freq, n, n, torch.complex64, dev)
+    pz, ldz, sz = _cm(Z, "Z")
+    p32, ld32, s32 = _cm(Z32, "Z32") if Z32 is not None else (0, 0, 0)
+    info = torch.empty(models.n_freq, dtype=torch.int32, device=dev)
+    x = x.contiguous()
+    y = y.contiguous()
+    check(lib().harp_fill(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
+                          models.Q, models.p_max, _ptr(x), _ptr(y), n_ant, float(ri), dt,
+                          pz, ldz, sz, p32, ld32, s32, _ptr(info), _stream(dev)), "harp_fill")
+    return Z, Z32, info
+
+
+def harp_port_rhs(models: ModelBatch, n_ant: int, B: torch.Tensor | None = None):
+    n = n_ant * models.n_mbf
+    dev = models.data.device
+    if B is None:
+        B = colmajor(models.n_freq, n, n_ant, torch.complex128, dev)
+    pb, ldb, sb = _cm(B, "B")
+    check(lib().harp_port_rhs(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
+                              n_ant, pb, ldb, sb, _stream(dev)), "harp_port_rhs")
+    return B
+
+
+def harp_port_admittance(models: ModelBatch, X: torch.Tensor, Y: torch.Tensor | None = None):
+    n_ant = X.shape[-1]
+    dev = models.data.device
+    if Y is None:
+        Y = colmajor(models.n_freq, n_ant, n_ant, torch.complex128, dev)
+    px, ldx, sx = _cm(X, "X")
+    py, ldy, sy = _cm(Y, "Y")
+    check(lib().harp_port_admittance(_ptr(models.data), models.stride, models.n_freq,
+                                     models.n_mbf, n_ant, px, ldx, sx, py, ldy, sy,
+                                     _stream(dev)), "harp_port_admittance")
+    return Y
+
+
+# --------------------------------------------------------------------------
+# factor, solve
+# --------------------------------------------------------------------------
+
+def reduced_factor(A: torch.Tensor):
+    """In-place LU with partial pivoting of a batch of column-major matrices.
+    Returns (ipiv, info) device tensors."""
+    if A.dim() == 2:
+        A = A.unsqueeze(0)
+    dt = _DT[A.dtype]
+    b, n, _ = A.shape
+    pa, lda, sa = _cm(A, "A")
+    ipiv = torch.empty((b, n), dtype=torch.int32, device=A.device)
+    info = torch.empty(b, dtype=torch.int32, device=A.device)
+    ws_b = ctypes.c_size_t()
+    check(lib().reduced_factor_ws(n, b, dt, ctypes.byref(ws_b)), "reduced_factor_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=A.device)
+    check(lib().reduced_factor(n, b, dt, pa, lda, sa, _ptr(ipiv), _ptr(info), _ptr(ws),
+                               ws_b.value, _stream(A.device)), "reduced_factor")
+    return ipiv, info
+
+
+def reduced_solve(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor,
+                  X: torch.Tensor | None = None, Z64: torch.Tensor | None = None,
+                  tol: float = 1e-12, max_iter: int = 10, raise_noconv: bool = True):
+    """Solve with the factors of reduced_factor; optional FP64 refinement
+    against Z64.  Returns (X, reports or None)."""
+    if LU.dim() == 2:
+        LU = LU.unsqueeze(0)
+    if B.dim() == 2:
+        B = B.unsqueeze(0)
+    dt = _DT[LU.dtype]
+    b, n, _ = LU.shape
+    nrhs = B.shape[-1]
+    if X is None:
+        X = colmajor(b, n, nrhs, torch.complex128, LU.device)
+    pl, lda, sl = _cm(LU, "LU")
+    pb, ldb, sb = _cm(B, "B")
+    px, ldx, sx = _cm(X, "X")
+    ref = None
+    rep = None
+    if Z64 is not None:
+        pz, ldz, sz = _cm(Z64, "Z64")
+        ref = HarpRefine(pz, ldz, sz, float(tol), int(max_iter))
+        rep = (HarpRefineReport * b)()
+    ws_b = ctypes.c_size_t()
+    check(lib().reduced_solve_ws(n, nrhs, b, dt, int(ref is not None), ctypes.byref(ws_b)),
+          "reduced_solve_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=LU.device)
+    st = lib().reduced_solve(n, nrhs, b, dt, pl, lda, sl, _ptr(ipiv), pb, ldb, sb, px, ldx, sx,
+                             ctypes.byref(ref) if ref is not None else None,
+                             rep if rep is not None else None, _ptr(ws), ws_b.value,
+                             _stream(LU.device))
+    if st == -4 and not raise_noconv:
+        st = 0
+    check(st, "reduced_solve")
+    reports = None
+    if rep is not None:
+        reports = [{"iters": r.iters, "converged": bool(r.converged), "resid_rel": r.resid_rel}
+                   for r in rep]
+    return X, reports
+
+
+# --------------------------------------------------------------------------
+# patterns
+# --------------------------------------------------------------------------
+
+def embedded_patterns(model: Model, x: torch.Tensor, y: torch.Tensor, X: torch.Tensor,
+                      theta: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:
+    """E[port, dir, (theta, phi)] complex128 for every column of X (Eqs. 5-6)."""
+    if X.dim() == 3:
+        X = X[0]
+    n_ant = int(x.numel())
+    n_ports = X.shape[-1]
+    n_dir = int(theta.numel())
+    px, ldx, _ = _cm(X, "X")
+    E = torch.empty((n_ports, n_dir, 2), dtype=torch.complex128, device=X.device)
+    check(lib().embedded_patterns(_ptr(model.blob), model.n_mbf, _ptr(x.contiguous()),
+                                  _ptr(y.contiguous()), n_ant, px, ldx, n_ports,
+                                  _ptr(theta.contiguous()), _ptr(phi.contiguous()), n_dir,
+                                  _ptr(E), _stream(X.device)), "embedded_patterns")
+    return E
+
+
+def to_device_samples(samples: np.ndarray, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(samples, dtype=np.float64)).to(device)
+
+
+def default_grid(P: int, Q: int):
+    return 4 * (P + 1), 2 * (Q + 1)
+
+
+__all__ = [
+    "Model", "ModelBatch", "harp_fit", "pack_model", "stack_models", "harp_fill",
+    "harp_port_rhs", "harp_port_admittance", "reduced_factor", "reduced_solve",
+    "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
+    "to_device_samples", "default_grid",
+]

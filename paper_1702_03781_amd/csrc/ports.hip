@@ -1,0 +1,96 @@
+// Port excitation and port admittances (Sections I and II-C).
+//
+// One port per element drives its MBFs with the weights w_T stored in the
+// model; a unit voltage at port j gives the right-hand side column
+// B[:, j] = e_j (x) w, and the current at port i of solution column j is
+// Y_ij = sum_T w_T X[i N_m + T, j]  (Y = W^T X).
+#include "common.hpp"
+
+namespace harp {
+namespace {
+
+// B (complex128, n x n_ant per frequency): one thread per entry.
+__global__ void __launch_bounds__(256)
+    port_rhs_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf, int n_ant,
+                    double2* __restrict__ B, int64_t ldb, int64_t stride_b) {
+    const int f = blockIdx.y;
+    const char* model = models + size_t(f) * model_stride;
+    const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
+    const double2* w = reinterpret_cast<const double2*>(model + h->off_port);
+    const int64_t n = int64_t(n_ant) * n_mbf;
+    const int64_t total = n * n_ant;
+    double2* Bf = B + size_t(f) * stride_b;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t col = e / n, row = e % n;
+        const int64_t ant = row / n_mbf, T = row % n_mbf;
+        double2 v = {0.0, 0.0};
+        if (ant == col) v = w[T];
+        Bf[col * ldb + row] = v;
+    }
+}
+
+// Y (complex128, n_ant x n_ant per frequency): one thread per entry.
+__global__ void __launch_bounds__(256)
+    port_admittance_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf,
+                           int n_ant, const double2* __restrict__ X, int64_t ldx, int64_t stride_x,
+                           double2* __restrict__ Y, int64_t ldy, int64_t stride_y) {
+    const int f = blockIdx.y;
+    const char* model = models + size_t(f) * model_stride;
+    const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
+    const double2* w = reinterpret_cast<const double2*>(model + h->off_port);
+    const int64_t total = int64_t(n_ant) * n_ant;
+    const double2* Xf = X + size_t(f) * stride_x;
+    double2* Yf = Y + size_t(f) * stride_y;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t j = e / n_ant, i = e % n_ant;
+        double re = 0.0, im = 0.0;
+        for (int T = 0; T < n_mbf; ++T) {
+            const double2 x = Xf[j * ldx + i * n_mbf + T];
+            const double2 ww = w[T];
+            re += ww.x * x.x - ww.y * x.y;
+            im += ww.x * x.y + ww.y * x.x;
+        }
+        Yf[j * ldy + i] = double2{re, im};
+    }
+}
+
+}  // namespace
+}  // namespace harp
+
+using namespace harp;
+
+extern "C" harp_status harp_port_rhs(const void* d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
+                                     int32_t n_ant, void* d_B, int64_t ldb, int64_t stride_b,
+                                     hipStream_t stream) {
+    if (!d_models || !d_B || n_freq <= 0 || n_freq > 65535 || n_mbf <= 0 || n_ant <= 0) return HARP_E_ARG;
+    const int64_t n = int64_t(n_ant) * n_mbf;
+    if (ldb < n || (n_freq > 1 && stride_b < ldb * n_ant)) return HARP_E_ARG;
+    const int64_t total = n * n_ant;
+    const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(port_rhs_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0, stream,
+                       static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                       static_cast<double2*>(d_B), ldb, stride_b);
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}
+
+extern "C" harp_status harp_port_admittance(const void* d_models, int64_t model_stride, int32_t n_freq,
+                                            int32_t n_mbf, int32_t n_ant, const void* d_X, int64_t ldx,
+                                            int64_t stride_x, void* d_Y, int64_t ldy, int64_t stride_y,
+                                            hipStream_t stream) {
+    if (!d_models || !d_X || !d_Y || n_freq <= 0 || n_freq > 65535 || n_mbf <= 0 || n_ant <= 0)
+        return HARP_E_ARG;
+    const int64_t n = int64_t(n_ant) * n_mbf;
+    if (ldx < n || ldy < n_ant) return HARP_E_ARG;
+    if (n_freq > 1 && (stride_x < ldx * n_ant || stride_y < ldy * n_ant)) return HARP_E_ARG;
+    const int64_t total = int64_t(n_ant) * n_ant;
+    const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
+    hipLaunchKernelGGL(port_admittance_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0, stream,
+                       static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                       static_cast<const double2*>(d_X), ldx, stride_x, static_cast<double2*>(d_Y), ldy,
+                       stride_y);
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}

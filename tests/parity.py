@@ -1,0 +1,55 @@
+"""Helpers shared by the GPU parity tests: error measures and conversion of
+oracle models into library model blobs (inputs only; no expected value ever
+comes from the GPU path)."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+from oracle import em, fit as ofit
+from workloads import workload
+
+
+def block_eps(Zg: np.ndarray, Zo: np.ndarray, n_mbf: int, offdiag_only: bool = True):
+    """Max over blocks of ||dZ_block||_F / ||Zo_block||_F (zero blocks must be
+    exactly zero), plus the global relative Frobenius error."""
+    n = Zo.shape[0]
+    na = n // n_mbf
+    D = (Zg - Zo).reshape(na, n_mbf, na, n_mbf)
+    O = Zo.reshape(na, n_mbf, na, n_mbf)
+    dn = np.sqrt((np.abs(D) ** 2).sum(axis=(1, 3)))
+    on = np.sqrt((np.abs(O) ** 2).sum(axis=(1, 3)))
+    mask = np.ones((na, na), bool)
+    if offdiag_only:
+        np.fill_diagonal(mask, False)
+    nz = mask & (on > 0)
+    zero = mask & (on == 0)
+    eps = float((dn[nz] / on[nz]).max()) if nz.any() else 0.0
+    zero_ok = bool((dn[zero] == 0).all()) if zero.any() else True
+    glob = float(np.linalg.norm(Zg - Zo) / np.linalg.norm(Zo))
+    return eps, zero_ok, glob
+
+
+def oracle_model(freq, elem, P, Q, r_min):
+    return ofit.fit(freq, elem.samples, P, Q, r_min, wire_radius=elem.wire_radius)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_models(cfg: str, wire_radius: float | None = None):
+    """Oracle models of a configuration (cached per process)."""
+    wl = workload(cfg)
+    if wire_radius is not None:
+        wl.elem.wire_radius = wire_radius
+    return wl, [oracle_model(f, wl.elem, P, wl.Q, wl.r_min) for f, P in zip(wl.freqs, wl.P)]
+
+
+def pack(api, m, device="cuda"):
+    """Oracle model -> library model blob (same numbers, as data)."""
+    return api.pack_model(m.C, m.Z_self, m.w, m.samples, m.freq, m.k, em.omega_mu(m.freq),
+                          m.r_min, m.wire_radius, device=device)
+
+
+def colmajor_to_numpy(M) -> np.ndarray:
+    """Batched column-major torch view (b, rows, cols) -> numpy (b, rows, cols)."""
+    return M.detach().cpu().numpy()

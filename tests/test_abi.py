@@ -1,0 +1,76 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/harp.h declares, and rejects bad arguments synchronously (no GPU
+work is enqueued for a rejected call, so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "harp.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_][a-z_0-9]*)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1702_03781_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["harp_fit", "harp_fill", "reduced_factor", "reduced_solve", "embedded_patterns",
+              "harp_port_rhs", "harp_port_admittance", "harp_model_bytes", "harp_fit_ws",
+              "reduced_factor_ws", "reduced_solve_ws", "harp_status_str", "harp_version"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for n in _declared():
+        assert hasattr(L, n), n
+
+
+def test_binding_signatures_cover_header():
+    from paper_1702_03781_amd import _lib
+    assert sorted(_lib.SIGNATURES) == _declared()
+
+
+def test_status_strings(L):
+    for s in range(0, -7, -1):
+        assert L.harp_status_str(s)
+    assert L.harp_version() >= 100
+
+
+def test_model_bytes_layout(L):
+    # header 256 + aligned sections
+    nb = L.harp_model_bytes(8, 64, 12, 6)
+    ncoef = 8 * 8 * 25 * 7
+    a = lambda b: (b + 255) & ~255  # noqa: E731
+    assert nb == 256 + a(ncoef * 16) + a(ncoef * 8) + a(64 * 16) + a(8 * 16) + a(8 * 64 * 64)
+    assert L.harp_model_bytes(0, 64, 12, 6) == 0
+
+
+def test_argument_errors_are_synchronous(L):
+    from paper_1702_03781_amd import _lib
+    HARP_E_ARG, HARP_E_WORKSPACE = -1, -6
+    # null pointers / bad sizes: rejected before any launch
+    assert L.harp_fill(None, 256, 1, 8, 6, 12, None, None, 16, 0.0, 0, None, 128, 0, None, 0, 0,
+                       None, None) == HARP_E_ARG
+    el = _lib.HarpElement(4, 32, 0, 0.02)
+    assert L.harp_fit(ctypes.byref(el), 1e8, 6, 6, 1.5, 28, 14, None, 0, None, 0, None) == HARP_E_ARG
+    el = _lib.HarpElement(4, 32, 1, 0.02)
+    # n_alpha odd -> invalid
+    assert L.harp_fit(ctypes.byref(el), 1e8, 6, 6, 1.5, 27, 14, 1, 1 << 20, 1, 1 << 20,
+                      None) == HARP_E_ARG
+    # workspace too small
+    assert L.harp_fit(ctypes.byref(el), 1e8, 6, 6, 1.5, 28, 14, 1, 1 << 20, 1, 16,
+                      None) == HARP_E_WORKSPACE
+    ws = ctypes.c_size_t()
+    assert L.harp_fit_ws(4, 32, 6, 6, 28, 14, ctypes.byref(ws)) == 0 and ws.value > 0

@@ -1,0 +1,137 @@
+"""GPU parity: model build (harp_fit) and Eq. (4) fill (harp_fill) against the
+FP64 CPU oracle, on the same seeded inputs, through the C ABI."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fill as ofill, fit as ofit, solve as osolve  # noqa: E402
+from workloads import element, layout_disk, workload  # noqa: E402
+
+from parity import block_eps, oracle_models, pack  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FILL_TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1702_03781_amd import api as A
+    return A
+
+
+def _gpu_fill(api, models_o, x, y, dtype, ri=0.0, dual=False):
+    mb = api.stack_models([pack(api, m) for m in models_o])
+    xt = torch.from_numpy(np.asarray(x, np.float64)).cuda()
+    yt = torch.from_numpy(np.asarray(y, np.float64)).cuda()
+    Z, Z32, info = api.harp_fill(mb, xt, yt, dtype=dtype, ri=ri, dual=dual)
+    torch.cuda.synchronize()
+    return Z.cpu().numpy(), (Z32.cpu().numpy() if Z32 is not None else None), info.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg,P_freq", [("cfg1", None), ("cfg2", 15)])
+def test_fit_matches_oracle(api, cfg, P_freq):
+    wl = workload(cfg)
+    i = 0 if P_freq is None else P_freq
+    f, P = wl.freqs[i], wl.P[i]
+    mo = ofit.fit(f, wl.elem.samples, P, wl.Q, wl.r_min, wire_radius=wl.elem.wire_radius)
+    s = api.to_device_samples(wl.elem.samples)
+    mg = api.harp_fit(s, wl.elem.wire_radius, f, P, wl.Q, wl.r_min)
+    torch.cuda.synchronize()
+    arr = api.model_arrays(mg)
+    scale = np.abs(mo.C).max()
+    assert np.abs(arr["C"] - mo.C).max() <= 1e-9 * scale
+    assert np.abs(arr["Z_self"] - mo.Z_self).max() <= 1e-12 * np.abs(mo.Z_self).max()
+    assert np.array_equal(arr["w"], mo.w)
+    assert np.array_equal(arr["C32"], arr["C"].astype(np.complex64))
+    h = arr["header"]
+    assert (h["n_mbf"], h["P"], h["Q"]) == (wl.elem.n_mbf, P, wl.Q)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fill_cfg1(api, dtype):
+    wl, models = oracle_models("cfg1")
+    Zg, _, info = _gpu_fill(api, models, wl.x, wl.y, dtype)
+    Zo = ofill.fill(models[0], wl.x, wl.y)
+    eps, zero_ok, _ = block_eps(Zg[0], Zo, wl.elem.n_mbf)
+    assert eps <= FILL_TOL[dtype], eps
+    nm = wl.elem.n_mbf
+    for a in range(wl.n_ant):
+        blk = Zg[0][a * nm:(a + 1) * nm, a * nm:(a + 1) * nm]
+        assert np.array_equal(blk, models[0].Z_self.astype(Zg.dtype))
+    assert info[0] == 0
+    # reciprocity of the GPU output
+    sym = np.abs(Zg[0] - Zg[0].T).max() / np.abs(Zg[0]).max()
+    assert sym <= (1e-13 if dtype == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("mode", ["c64", "c128", "dual"])
+def test_fill_cfg2_all_frequencies(api, mode):
+    """Full station sweep (256 elements, 8 MBFs, 16 frequencies), every block."""
+    wl, models = oracle_models("cfg2")
+    dtype = "c64" if mode == "c64" else "c128"
+    Zg, Z32, info = _gpu_fill(api, models, wl.x, wl.y, dtype, dual=(mode == "dual"))
+    assert (info == 0).all()
+    for f, m in enumerate(models):
+        Zo = ofill.fill(m, wl.x, wl.y)
+        eps, _, glob = block_eps(Zg[f], Zo, wl.elem.n_mbf)
+        assert eps <= FILL_TOL[dtype], (f, eps)
+        if mode == "dual":
+            # the complex64 copy is the rounding of the FP64 result
+            assert np.array_equal(Z32[f], Zg[f].astype(np.complex64))
+
+
+def test_fill_ragged_and_radius_of_influence(api):
+    """37 antennas (a ragged tile), 3 MBFs, Q = 4, and a radius of influence."""
+    el = element(3, 9, seed=77)
+    x, y = layout_disk(37, 9.0, 1.2, seed=78)
+    P, Q = 5, 4
+    mo = ofit.fit(130e6, el.samples, P, Q, 1.2, wire_radius=el.wire_radius)
+    for ri in (0.0, 6.0):
+        for dtype in ("c128", "c64"):
+            Zg, _, info = _gpu_fill(api, [mo], x, y, dtype, ri=ri)
+            Zo = ofill.fill(mo, x, y, ri=ri)
+            eps, zero_ok, _ = block_eps(Zg[0], Zo, 3)
+            assert eps <= FILL_TOL[dtype]
+            assert zero_ok
+            assert info[0] == 0
+
+
+def test_fill_counts_pairs_below_rmin(api):
+    wl, models = oracle_models("cfg1")
+    x = wl.x.copy()
+    y = wl.y.copy()
+    x[5] = x[4] + 0.7          # one pair closer than r_min = 1.5 m
+    y[5] = y[4]
+    _, _, info = _gpu_fill(api, models, x, y, "c64")
+    assert info[0] == ofill.count_below_rmin(models[0], x, y) >= 2
+
+
+def test_fill_rejects_mismatched_model(api):
+    wl, models = oracle_models("cfg1")
+    mb = api.stack_models([pack(api, models[0])])
+    mb.n_mbf = 3               # wrong element size for this blob
+    xt = torch.from_numpy(wl.x[:10].copy()).cuda()
+    yt = torch.from_numpy(wl.y[:10].copy()).cuda()
+    _, _, info = api.harp_fill(mb, xt, yt, dtype="c64")
+    torch.cuda.synchronize()
+    assert info.cpu().numpy()[0] == -1
+
+
+def test_ports_rhs_and_admittance(api):
+    wl, models = oracle_models("cfg1")
+    m = models[0]
+    mb = api.stack_models([pack(api, m)])
+    B = api.harp_port_rhs(mb, wl.n_ant)
+    torch.cuda.synchronize()
+    Bo = osolve.port_rhs(m.w, wl.n_ant)
+    assert np.array_equal(B.cpu().numpy()[0], Bo)
+    Zo = ofill.fill(m, wl.x, wl.y)
+    Xo = osolve.solve(Zo, Bo)
+    Xt = api.colmajor(1, Xo.shape[0], Xo.shape[1], torch.complex128, "cuda")
+    Xt.copy_(torch.from_numpy(Xo)[None])
+    Y = api.harp_port_admittance(mb, Xt)
+    torch.cuda.synchronize()
+    Yo = osolve.admittance(Xo, m.w, wl.n_ant)
+    assert np.abs(Y.cpu().numpy()[0] - Yo).max() <= 1e-14 * np.abs(Yo).max()
