@@ -59,6 +59,13 @@ SIGNATURES = {
 }
 
 
+# test hook declared in include/harp_debug.h (not part of the boundary)
+DEBUG_SIGNATURES = {
+    "harp_debug_cgemm": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_vp, c_i64, c_i64, c_vp,
+                                 c_i64, c_i64, c_dbl, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
+}
+
+
 def lib():
     """Load libharp.so (raises if it has not been built)."""
     global _lib
@@ -68,7 +75,7 @@ def lib():
                                "`python -m paper_1702_03781_amd.build` (or "
                                "__graft_entry__.build()) first")
         L = ctypes.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
+        for name, (res, args) in {**SIGNATURES, **DEBUG_SIGNATURES}.items():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args

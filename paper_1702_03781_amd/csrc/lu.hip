@@ -1,0 +1,840 @@
+// Dense reduced solve: blocked LU with partial pivoting, triangular solves and
+// FP64 iterative refinement, batched over independent systems (frequencies,
+// layouts).
+//
+// The reduced MoM system of order n = N_a N_m is solved by Gaussian
+// elimination, one right-hand side per antenna port (Section I; the solve is
+// the O((N_a N_m)^3) part of Section II-B and the "Solving MoM equations" row
+// of Table II).
+//
+// Factorisation (right-looking, outer block nb, inner panels of W columns):
+//   for each outer block [k0, k0+nb):
+//     for each inner panel [j0, j0+W):
+//       getf2_kernel   : pivot search, swap, scale and rank-1 updates of the
+//                        panel held in registers (one workgroup per matrix);
+//                        the panel's row exchanges applied to the other
+//                        columns of the outer block; unit-lower solve of the
+//                        outer block's columns to the right of the panel
+//       cgemm          : update of the rest of the outer block (MFMA)
+//     laswp_trsm_kernel: row exchanges + unit-lower solve of the block row U12
+//     cgemm            : trailing update A22 -= L21 U12 (MFMA, the hot loop)
+// Row exchanges of a later outer block are not applied to the multipliers of
+// earlier blocks; the forward solve applies the exchanges block by block in
+// the same order, which is equivalent (the multipliers of block K are stored
+// in the row order current at step K).
+#include <float.h>
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "cgemm.hpp"
+#include "common.hpp"
+
+namespace harp {
+namespace {
+
+template <typename T> struct C2;
+template <> struct C2<float> { using t = float2; };
+template <> struct C2<double> { using t = double2; };
+
+template <typename V> __device__ inline V cm(V a, V b) {
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename V> __device__ inline V cfms(V acc, V a, V b) {   // acc - a * b
+    acc.x = fma(-a.x, b.x, fma(a.y, b.y, acc.x));
+    acc.y = fma(-a.x, b.y, fma(-a.y, b.x, acc.y));
+    return acc;
+}
+template <typename V> __device__ inline V crecip(V a) {
+    // 1 / a with scaling (Smith's method) to avoid overflow in |a|^2
+    using R = decltype(a.x);
+    if (fabs(a.x) >= fabs(a.y)) {
+        const R r = a.y / a.x, d = a.x + a.y * r;
+        return V{R(1) / d, -r / d};
+    }
+    const R r = a.x / a.y, d = a.y + a.x * r;
+    return V{r / d, R(-1) / d};
+}
+
+// ---------------------------------------------------------------------------
+// panel factorisation
+// ---------------------------------------------------------------------------
+
+struct PanelArgs {
+    void* A;
+    int64_t lda, sA;
+    int n, k0, kend, j0, w;
+    int32_t* ipiv;      // [batch][n]
+    int32_t* info;      // [batch]
+};
+
+template <typename T, int NT, int RPT, int W>
+__global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
+    using V = typename C2<T>::t;
+    constexpr int NW = NT / 64;
+    const int b = blockIdx.x;
+    V* A = reinterpret_cast<V*>(pa.A) + size_t(b) * pa.sA;
+    const int64_t lda = pa.lda;
+    const int n = pa.n, j0 = pa.j0, w = pa.w;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    __shared__ T red_v[2][NW];
+    __shared__ int red_i[2][NW];
+    __shared__ V prow[2][W];
+    __shared__ V jrow[2][W];
+    __shared__ V Ls[W][W];
+    __shared__ int piv_s[W];
+
+    V a[RPT][W];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = j0 + tid + r * NT;
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            a[r][c] = (row < n && c < w) ? A[size_t(j0 + c) * lda + row] : V{T(0), T(0)};
+    }
+
+#pragma unroll
+    for (int jj = 0; jj < W; ++jj) {
+        if (jj >= w) break;
+        const int par = jj & 1;
+        const int j = j0 + jj;
+        // local candidate: first row maximising |re| + |im| among rows >= j
+        // best = -1 with the diagonal row as default keeps p inside [j, n) even
+        // when the column holds NaN
+        T best = T(-1);
+        int bidx = j;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            const V v = a[r][jj];
+            const T m = fabs(v.x) + fabs(v.y);
+            if (row >= j && row < n && (m > best || (m == best && row < bidx))) {
+                best = m;
+                bidx = row;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const T ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bidx, off, 64);
+            if (ob > best || (ob == best && oi < bidx)) {
+                best = ob;
+                bidx = oi;
+            }
+        }
+        if (lane == 0) {
+            red_v[par][wave] = best;
+            red_i[par][wave] = bidx;
+        }
+        __syncthreads();
+        best = red_v[par][0];
+        bidx = red_i[par][0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            const T ob = red_v[par][q];
+            const int oi = red_i[par][q];
+            if (ob > best || (ob == best && oi < bidx)) {
+                best = ob;
+                bidx = oi;
+            }
+        }
+        const int p = bidx;
+        const int own_p = (p - j0) % NT, slot_p = (p - j0) / NT;
+        const int own_j = (j - j0) % NT, slot_j = (j - j0) / NT;
+        if (tid == own_p) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (r == slot_p)
+#pragma unroll
+                    for (int c = 0; c < W; ++c) prow[par][c] = a[r][c];
+        }
+        if (tid == own_j) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+                if (r == slot_j)
+#pragma unroll
+                    for (int c = 0; c < W; ++c) jrow[par][c] = a[r][c];
+        }
+        if (tid == 0) {
+            piv_s[jj] = p;
+            pa.ipiv[size_t(b) * n + j] = p;
+            if (best == T(0)) atomicCAS(pa.info + b, 0, j + 1);
+        }
+        __syncthreads();
+        // exchange rows j and p
+        if (p != j) {
+            if (tid == own_j) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+                    if (r == slot_j)
+#pragma unroll
+                        for (int c = 0; c < W; ++c) a[r][c] = prow[par][c];
+            }
+            if (tid == own_p) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+                    if (r == slot_p)
+#pragma unroll
+                        for (int c = 0; c < W; ++c) a[r][c] = jrow[par][c];
+            }
+        }
+        // scale the column below the pivot and update the rest of the panel
+        const V piv = prow[par][jj];
+        const bool nz = best != T(0);
+        const V inv = nz ? crecip(piv) : V{T(0), T(0)};
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            if (row > j && row < n && nz) {
+                const V l = cm(a[r][jj], inv);
+                a[r][jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < W; ++c)
+                    if (c < w) a[r][c] = cfms(a[r][c], l, prow[par][c]);
+            }
+        }
+    }
+
+    // write the panel back; keep its unit-lower top block in LDS
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = j0 + tid + r * NT;
+        if (row < n) {
+#pragma unroll
+            for (int c = 0; c < W; ++c)
+                if (c < w) A[size_t(j0 + c) * lda + row] = a[r][c];
+        }
+        if (r == 0 && tid < w) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) Ls[tid][c] = a[0][c];
+        }
+    }
+    __syncthreads();
+
+    // other columns of the outer block: row exchanges of this panel, then the
+    // unit-lower solve for the columns right of the panel
+    const int left = j0 - pa.k0;
+    const int right = pa.kend - (j0 + w);
+    for (int e = tid; e < left + right; e += NT) {
+        const int col = e < left ? pa.k0 + e : j0 + w + (e - left);
+        V* Ac = A + size_t(col) * lda;
+        for (int q = 0; q < w; ++q) {
+            const int pr = piv_s[q];
+            if (pr != j0 + q) {
+                const V t0 = Ac[j0 + q];
+                Ac[j0 + q] = Ac[pr];
+                Ac[pr] = t0;
+            }
+        }
+        if (e >= left) {
+            V x[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) x[i] = i < w ? Ac[j0 + i] : V{T(0), T(0)};
+#pragma unroll
+            for (int i = 1; i < W; ++i)
+#pragma unroll
+                for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[i][q], x[q]);
+#pragma unroll
+            for (int i = 0; i < W; ++i)
+                if (i < w) Ac[j0 + i] = x[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// row exchanges + unit-lower solve of a block row (trailing columns of the
+// factorisation, or the right-hand sides in the forward solve)
+// ---------------------------------------------------------------------------
+
+struct TrsmArgs {
+    const void* LU;
+    int64_t lda, sL;
+    const int32_t* ipiv;   // [batch][n]
+    int n, k0, nbo;
+    void* X;
+    int64_t ldx, sX;
+    int c_begin, c_end;    // columns of X to process
+    const int32_t* active;
+};
+
+// The solves work on 16-row chunks: a chunk is loaded, updated with the
+// already final chunks (re-read from memory, L1-resident), solved in
+// registers and stored, so each thread holds at most two chunks.
+constexpr int kCh = 16;
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(64) laswp_trsm_lower_kernel(TrsmArgs ta) {
+    using V = typename C2<T>::t;
+    static_assert(NB % kCh == 0, "block size");
+    const int b = blockIdx.y;
+    if (ta.active && ta.active[b] == 0) return;
+    const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
+    V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
+    const int32_t* ipiv = ta.ipiv + size_t(b) * ta.n;
+    const int k0 = ta.k0, nbo = ta.nbo;
+    __shared__ V Ls[NB][NB + 1];
+    __shared__ int pv[NB];
+    for (int e = threadIdx.x; e < NB * NB; e += 64) {
+        const int i = e % NB, j = e / NB;
+        Ls[i][j] = (i < nbo && j < nbo) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+    }
+    for (int e = threadIdx.x; e < nbo; e += 64) pv[e] = ipiv[k0 + e];
+    __syncthreads();
+    const int col = ta.c_begin + blockIdx.x * 64 + threadIdx.x;
+    if (col >= ta.c_end) return;
+    V* Xc = X + size_t(col) * ta.ldx + k0;
+    for (int q = 0; q < nbo; ++q) {
+        const int pr = pv[q] - k0;
+        if (pr != q) {
+            const V t0 = Xc[q];
+            Xc[q] = Xc[pr];
+            Xc[pr] = t0;
+        }
+    }
+    const int nch = (nbo + kCh - 1) / kCh;
+    for (int c = 0; c < nch; ++c) {
+        V x[kCh];
+#pragma unroll
+        for (int i = 0; i < kCh; ++i) x[i] = (c * kCh + i < nbo) ? Xc[c * kCh + i] : V{T(0), T(0)};
+        for (int p = 0; p < c; ++p) {
+            V y[kCh];
+#pragma unroll
+            for (int q = 0; q < kCh; ++q) y[q] = Xc[p * kCh + q];
+#pragma unroll
+            for (int i = 0; i < kCh; ++i)
+#pragma unroll
+                for (int q = 0; q < kCh; ++q) x[i] = cfms(x[i], Ls[c * kCh + i][p * kCh + q], y[q]);
+        }
+#pragma unroll
+        for (int i = 1; i < kCh; ++i)
+#pragma unroll
+            for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[c * kCh + i][c * kCh + q], x[q]);
+#pragma unroll
+        for (int i = 0; i < kCh; ++i)
+            if (c * kCh + i < nbo) Xc[c * kCh + i] = x[i];
+    }
+}
+
+// upper solve with the non-unit diagonal block U11 (backward substitution)
+template <typename T, int NB>
+__global__ void __launch_bounds__(64) trsm_upper_kernel(TrsmArgs ta) {
+    using V = typename C2<T>::t;
+    static_assert(NB % kCh == 0, "block size");
+    const int b = blockIdx.y;
+    if (ta.active && ta.active[b] == 0) return;
+    const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
+    V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
+    const int k0 = ta.k0, nbo = ta.nbo;
+    __shared__ V Us[NB][NB + 1];
+    __shared__ V dinv[NB];
+    for (int e = threadIdx.x; e < NB * NB; e += 64) {
+        const int i = e % NB, j = e / NB;
+        Us[i][j] = (i < nbo && j < nbo) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NB; e += 64) dinv[e] = e < nbo ? crecip(Us[e][e]) : V{T(0), T(0)};
+    __syncthreads();
+    const int col = ta.c_begin + blockIdx.x * 64 + threadIdx.x;
+    if (col >= ta.c_end) return;
+    V* Xc = X + size_t(col) * ta.ldx + k0;
+    const int nch = (nbo + kCh - 1) / kCh;
+    for (int c = nch - 1; c >= 0; --c) {
+        V x[kCh];
+#pragma unroll
+        for (int i = 0; i < kCh; ++i) x[i] = (c * kCh + i < nbo) ? Xc[c * kCh + i] : V{T(0), T(0)};
+        for (int p = c + 1; p < nch; ++p) {
+            V y[kCh];
+#pragma unroll
+            for (int q = 0; q < kCh; ++q) y[q] = (p * kCh + q < nbo) ? Xc[p * kCh + q] : V{T(0), T(0)};
+#pragma unroll
+            for (int i = 0; i < kCh; ++i)
+#pragma unroll
+                for (int q = 0; q < kCh; ++q) x[i] = cfms(x[i], Us[c * kCh + i][p * kCh + q], y[q]);
+        }
+#pragma unroll
+        for (int i = kCh - 1; i >= 0; --i) {
+#pragma unroll
+            for (int q = i + 1; q < kCh; ++q) x[i] = cfms(x[i], Us[c * kCh + i][c * kCh + q], x[q]);
+            x[i] = cm(x[i], dinv[c * kCh + i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kCh; ++i)
+            if (c * kCh + i < nbo) Xc[c * kCh + i] = x[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small helpers: zero info, conversions, Frobenius norms, axpy
+// ---------------------------------------------------------------------------
+
+__global__ void zero_i32(int32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(256) convert_kernel(const Ti* __restrict__ src, int64_t lds, int64_t ss,
+                                                      To* __restrict__ dst, int64_t ldd, int64_t sd, int rows,
+                                                      int cols, const int32_t* active) {
+    const int b = blockIdx.z;
+    if (active && active[b] == 0) return;
+    const int64_t total = int64_t(rows) * cols;
+    src += size_t(b) * ss;
+    dst += size_t(b) * sd;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = e / rows, r = e % rows;
+        const Ti v = src[c * lds + r];
+        To o;
+        o.x = decltype(o.x)(v.x);
+        o.y = decltype(o.y)(v.y);
+        dst[c * ldd + r] = o;
+    }
+}
+
+// X += D (complex128 += complex64 or complex128)
+template <typename Vd>
+__global__ void __launch_bounds__(256) axpy_kernel(double2* __restrict__ X, int64_t ldx, int64_t sx,
+                                                   const Vd* __restrict__ D, int64_t ldd, int64_t sd, int rows,
+                                                   int cols, const int32_t* active) {
+    const int b = blockIdx.z;
+    if (active && active[b] == 0) return;
+    const int64_t total = int64_t(rows) * cols;
+    X += size_t(b) * sx;
+    D += size_t(b) * sd;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = e / rows, r = e % rows;
+        const Vd d = D[c * ldd + r];
+        double2 x = X[c * ldx + r];
+        x.x += double(d.x);
+        x.y += double(d.y);
+        X[c * ldx + r] = x;
+    }
+}
+
+// sum of |v|^2 over a column-major complex128 matrix: per-block partials
+constexpr int kNormBlocks = 64;
+__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M, int64_t ld, int64_t s,
+                                                            int rows, int cols, double* __restrict__ part) {
+    const int b = blockIdx.z;
+    M += size_t(b) * s;
+    const int64_t total = int64_t(rows) * cols;
+    double acc = 0.0;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t c = e / rows, r = e % rows;
+        const double2 v = M[c * ld + r];
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[size_t(b) * kNormBlocks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+__global__ void sumsq_final_kernel(const double* __restrict__ part, double* __restrict__ out, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double s = 0.0;
+    for (int i = 0; i < kNormBlocks; ++i) s += part[size_t(b) * kNormBlocks + i];
+    out[b] = sqrt(s);
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+
+template <typename T> struct LuCfg {
+    static constexpr int NB = 64;   // outer block (row/column block of the trailing update)
+};
+
+// Panel width: the register-resident panel holds RPT x W complex values per
+// thread; W shrinks as the matrix grows so the panel stays in registers.
+template <typename T> inline int panel_width(int n) {
+    const int base = sizeof(T) == 4 ? 16 : 8;
+    return n <= 2048 ? base : (n <= 4096 ? base / 2 : base / 4);
+}
+
+template <typename T, int W>
+harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
+    const int m = pa.n - pa.j0;
+    constexpr int W8 = W > 8 ? 8 : W, W4 = W > 4 ? 4 : W;
+    if ((m > 512 * 4 && pa.w > W8) || (m > 512 * 8 && pa.w > W4)) return HARP_E_ARG;
+    if (m <= 512 * 4) {
+        hipLaunchKernelGGL((getf2_kernel<T, 512, 4, W>), dim3(batch), dim3(512), 0, st, pa);
+    } else if (m <= 512 * 8) {
+        hipLaunchKernelGGL((getf2_kernel<T, 512, 8, W8>), dim3(batch), dim3(512), 0, st, pa);
+    } else if (m <= 1024 * 8) {
+        hipLaunchKernelGGL((getf2_kernel<T, 1024, 8, W4>), dim3(batch), dim3(1024), 0, st, pa);
+    } else {
+        return HARP_E_ARG;
+    }
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}
+
+template <typename T>
+harp_status launch_getf2(const PanelArgs& pa, int W, int batch, hipStream_t st) {
+    if (pa.w > W) return HARP_E_ARG;
+    switch (W) {
+        case 16: return launch_getf2_w<T, 16>(pa, batch, st);
+        case 8: return launch_getf2_w<T, 8>(pa, batch, st);
+        case 4: return launch_getf2_w<T, 4>(pa, batch, st);
+        case 2: return launch_getf2_w<T, 2>(pa, batch, st);
+    }
+    return HARP_E_ARG;
+}
+
+template <typename T>
+GemmArgs<T> sub_gemm(T* base, int64_t ld, int64_t s, int M, int N, int K, int ar, int ac, int br, int bc, int cr,
+                     int cc, T alpha, T beta, const int32_t* active) {
+    GemmArgs<T> g;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = base + 2 * (size_t(ac) * ld + ar);
+    g.lda = ld;
+    g.sA = s;
+    g.B = base + 2 * (size_t(bc) * ld + br);
+    g.ldb = ld;
+    g.sB = s;
+    g.C = base + 2 * (size_t(cc) * ld + cr);
+    g.ldc = ld;
+    g.sC = s;
+    g.D = const_cast<T*>(g.C);
+    g.ldd = ld;
+    g.sD = s;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.active = active;
+    return g;
+}
+
+template <typename T>
+harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t* ipiv, int32_t* info,
+                        hipStream_t st) {
+    constexpr int NB = LuCfg<T>::NB;
+    const int W = panel_width<T>(n);
+    hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch);
+    HARP_LAUNCH_CHECK();
+    harp_status s;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
+        for (int j0 = k0; j0 < kend; j0 += W) {
+            const int w = std::min(W, kend - j0);
+            PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info};
+            if ((s = launch_getf2<T>(pa, W, batch, st)) != HARP_OK) return s;
+            if (j0 + w < kend) {
+                GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - j0 - w, kend - j0 - w, w, j0 + w, j0, j0, j0 + w,
+                                            j0 + w, j0 + w, T(-1), T(1), nullptr);
+                if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+            }
+        }
+        if (kend < n) {
+            TrsmArgs ta{A, lda, sA, ipiv, n, k0, nbo, A, lda, sA, kend, n, nullptr};
+            const int ncol = n - kend;
+            hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3((ncol + 63) / 64, batch), dim3(64), 0, st, ta);
+            HARP_LAUNCH_CHECK();
+            GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - kend, n - kend, nbo, kend, k0, k0, kend, kend, kend, T(-1),
+                                        T(1), nullptr);
+            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+        }
+    }
+    return HARP_OK;
+}
+
+// in-place solve of X (n x nrhs, same precision as the factors)
+template <typename T>
+harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int64_t sL, const int32_t* ipiv, T* X,
+                       int64_t ldx, int64_t sX, const int32_t* active, hipStream_t st) {
+    constexpr int NB = LuCfg<T>::NB;
+    harp_status s;
+    const dim3 tgrid((nrhs + 63) / 64, batch);
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
+        TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
+        hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), tgrid, dim3(64), 0, st, ta);
+        HARP_LAUNCH_CHECK();
+        if (kend < n) {
+            GemmArgs<T> g;
+            g.M = n - kend;
+            g.N = nrhs;
+            g.K = nbo;
+            g.A = LU + 2 * (size_t(k0) * lda + kend);
+            g.lda = lda;
+            g.sA = sL;
+            g.B = X + 2 * size_t(k0);
+            g.ldb = ldx;
+            g.sB = sX;
+            g.C = X + 2 * size_t(kend);
+            g.ldc = ldx;
+            g.sC = sX;
+            g.D = X + 2 * size_t(kend);
+            g.ldd = ldx;
+            g.sD = sX;
+            g.alpha = T(-1);
+            g.beta = T(1);
+            g.active = active;
+            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+        }
+    }
+    const int nblk = (n + NB - 1) / NB;
+    for (int bk = nblk - 1; bk >= 0; --bk) {
+        const int k0 = bk * NB, nbo = std::min(NB, n - k0);
+        TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
+        hipLaunchKernelGGL((trsm_upper_kernel<T, NB>), tgrid, dim3(64), 0, st, ta);
+        HARP_LAUNCH_CHECK();
+        if (k0 > 0) {
+            GemmArgs<T> g;
+            g.M = k0;
+            g.N = nrhs;
+            g.K = nbo;
+            g.A = LU + 2 * (size_t(k0) * lda);
+            g.lda = lda;
+            g.sA = sL;
+            g.B = X + 2 * size_t(k0);
+            g.ldb = ldx;
+            g.sB = sX;
+            g.C = X;
+            g.ldc = ldx;
+            g.sC = sX;
+            g.D = X;
+            g.ldd = ldx;
+            g.sD = sX;
+            g.alpha = T(-1);
+            g.beta = T(1);
+            g.active = active;
+            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+        }
+    }
+    return HARP_OK;
+}
+
+template <typename Ti, typename To>
+harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t ldd, int64_t sd, int rows, int cols,
+                    int batch, const int32_t* active, hipStream_t st) {
+    const int64_t total = int64_t(rows) * cols;
+    const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 2048));
+    hipLaunchKernelGGL((convert_kernel<Ti, To>), dim3(blocks, 1, batch), dim3(256), 0, st,
+                       static_cast<const Ti*>(src), lds, ss, static_cast<To*>(dst), ldd, sd, rows, cols, active);
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}
+
+harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, int batch, double* part, double* out,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 1, batch), dim3(256), 0, st,
+                       static_cast<const double2*>(M), ld, s, rows, cols, part);
+    HARP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(sumsq_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, part, out, batch);
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}
+
+struct SolveWs {
+    float2* B32;      // n x nrhs complex64 per matrix (ld n)
+    double2* R;       // n x nrhs complex128 per matrix (ld n)
+    double* part;     // [batch][kNormBlocks]
+    double* norms;    // [3][batch]: ||Z||, ||R||, ||X||
+    int32_t* active;  // [batch]
+};
+
+size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveWs* w, char* base) {
+    const int64_t mat = int64_t(n) * nrhs;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off += align256(bytes);
+        return base ? base + o : nullptr;
+    };
+    SolveWs tmp{};
+    SolveWs& W = w ? *w : tmp;
+    W.B32 = reinterpret_cast<float2*>(take((dtype == HARP_C64) ? mat * batch * 8 : 0));
+    W.R = reinterpret_cast<double2*>(take(refine ? mat * batch * 16 : 0));
+    W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * kNormBlocks * 8 : 0));
+    W.norms = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 3 * 8 : 0));
+    W.active = reinterpret_cast<int32_t*>(take(refine ? int64_t(batch) * 4 : 0));
+    return size_t(off);
+}
+
+}  // namespace
+}  // namespace harp
+
+using namespace harp;
+
+extern "C" harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t* bytes) {
+    if (!bytes || n <= 0 || batch <= 0 || (dtype != HARP_C64 && dtype != HARP_C128)) return HARP_E_ARG;
+    *bytes = 0;
+    return HARP_OK;
+}
+
+extern "C" harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void* d_A, int64_t lda,
+                                      int64_t stride_a, int32_t* d_ipiv, int32_t* d_info, void* d_ws, size_t ws_bytes,
+                                      hipStream_t stream) {
+    (void)d_ws;
+    (void)ws_bytes;
+    if (!d_A || !d_ipiv || !d_info || n <= 0 || batch <= 0 || batch > 65535) return HARP_E_ARG;
+    if (n > 8192) return HARP_E_ARG;
+    if (lda < n || (batch > 1 && stride_a < lda * n)) return HARP_E_ARG;
+    if (dtype == HARP_C64)
+        return factor_impl<float>(n, batch, static_cast<float*>(d_A), lda, stride_a, d_ipiv, d_info, stream);
+    if (dtype == HARP_C128)
+        return factor_impl<double>(n, batch, static_cast<double*>(d_A), lda, stride_a, d_ipiv, d_info, stream);
+    return HARP_E_ARG;
+}
+
+extern "C" harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, int32_t refine,
+                                        size_t* bytes) {
+    if (!bytes || n <= 0 || nrhs <= 0 || batch <= 0 || (dtype != HARP_C64 && dtype != HARP_C128)) return HARP_E_ARG;
+    *bytes = solve_ws_layout(n, nrhs, batch, dtype, refine, nullptr, nullptr);
+    return HARP_OK;
+}
+
+extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, const void* d_LU,
+                                     int64_t lda, int64_t stride_lu, const int32_t* d_ipiv, const void* d_B,
+                                     int64_t ldb, int64_t stride_b, void* d_X, int64_t ldx, int64_t stride_x,
+                                     const harp_refine* refine, harp_refine_report* report, void* d_ws,
+                                     size_t ws_bytes, hipStream_t st) {
+    if (!d_LU || !d_ipiv || !d_B || !d_X || n <= 0 || nrhs <= 0 || batch <= 0 || batch > 65535) return HARP_E_ARG;
+    if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
+    if (lda < n || ldb < n || ldx < n) return HARP_E_ARG;
+    if (batch > 1 && (stride_lu < lda * n || stride_b < ldb * nrhs || stride_x < ldx * nrhs)) return HARP_E_ARG;
+    const bool ref = refine != nullptr;
+    if (ref) {
+        if (!refine->d_Z || refine->ldz < n || refine->max_iter < 0 || !(refine->tol >= 0.0)) return HARP_E_ARG;
+        if (batch > 1 && refine->stride_z < refine->ldz * n) return HARP_E_ARG;
+    }
+    const size_t need = solve_ws_layout(n, nrhs, batch, dtype, ref, nullptr, nullptr);
+    if (need > 0 && (!d_ws || ws_bytes < need)) return HARP_E_WORKSPACE;
+    SolveWs W{};
+    solve_ws_layout(n, nrhs, batch, dtype, ref, &W, static_cast<char*>(d_ws));
+    const int64_t mat = int64_t(n) * nrhs;
+    harp_status s;
+
+    // first solve in the factor precision, result promoted into X
+    auto solve_into = [&](const void* rhs, int64_t ldr, int64_t sr, const int32_t* active, bool accumulate) {
+        if (dtype == HARP_C64) {
+            if ((s = convert<double2, float2>(rhs, ldr, sr, W.B32, n, mat, n, nrhs, batch, active, st)) != HARP_OK)
+                return s;
+            if ((s = solve_impl<float>(n, nrhs, batch, static_cast<const float*>(d_LU), lda, stride_lu, d_ipiv,
+                                       reinterpret_cast<float*>(W.B32), n, mat, active, st)) != HARP_OK)
+                return s;
+            if (accumulate) {
+                const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
+                hipLaunchKernelGGL(axpy_kernel<float2>, dim3(blocks, 1, batch), dim3(256), 0, st,
+                                   static_cast<double2*>(d_X), ldx, stride_x, W.B32, n, mat, n, nrhs, active);
+                HARP_LAUNCH_CHECK();
+                return HARP_OK;
+            }
+            return convert<float2, double2>(W.B32, n, mat, d_X, ldx, stride_x, n, nrhs, batch, active, st);
+        }
+        // complex128 factors: solve directly in X (corrections take the branch in the loop)
+        if ((s = convert<double2, double2>(rhs, ldr, sr, d_X, ldx, stride_x, n, nrhs, batch, active, st)) != HARP_OK)
+            return s;
+        return solve_impl<double>(n, nrhs, batch, static_cast<const double*>(d_LU), lda, stride_lu, d_ipiv,
+                                  static_cast<double*>(d_X), ldx, stride_x, active, st);
+    };
+
+    if ((s = solve_into(d_B, ldb, stride_b, nullptr, false)) != HARP_OK) return s;
+    if (!ref) return HARP_OK;
+
+    // FP64 iterative refinement
+    std::vector<double> hn(3 * size_t(batch));
+    std::vector<int32_t> act(batch, 1), iters(batch, 0), conv(batch, 0);
+    std::vector<double> rel(batch, 0.0);
+    if ((s = fro_norms(refine->d_Z, refine->ldz, refine->stride_z, n, n, batch, W.part, W.norms, st)) != HARP_OK)
+        return s;
+    HARP_HIP_CHECK(hipMemcpyAsync(W.active, act.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+    for (int it = 0;; ++it) {
+        // R = B - Z X  (FP64, MFMA)
+        GemmArgs<double> g;
+        g.M = n;
+        g.N = nrhs;
+        g.K = n;
+        g.A = static_cast<const double*>(refine->d_Z);
+        g.lda = refine->ldz;
+        g.sA = refine->stride_z;
+        g.B = static_cast<const double*>(d_X);
+        g.ldb = ldx;
+        g.sB = stride_x;
+        g.C = static_cast<const double*>(d_B);
+        g.ldc = ldb;
+        g.sC = stride_b;
+        g.D = reinterpret_cast<double*>(W.R);
+        g.ldd = n;
+        g.sD = mat;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        g.active = W.active;
+        if ((s = cgemm<double>(g, batch, st)) != HARP_OK) return s;
+        if ((s = fro_norms(W.R, n, mat, n, nrhs, batch, W.part, W.norms + batch, st)) != HARP_OK) return s;
+        if ((s = fro_norms(d_X, ldx, stride_x, n, nrhs, batch, W.part, W.norms + 2 * batch, st)) != HARP_OK) return s;
+        HARP_HIP_CHECK(hipMemcpyAsync(hn.data(), W.norms, sizeof(double) * 3 * batch, hipMemcpyDeviceToHost, st));
+        HARP_HIP_CHECK(hipStreamSynchronize(st));
+        int n_active = 0;
+        for (int b = 0; b < batch; ++b) {
+            if (!act[b]) continue;
+            const double denom = hn[b] * hn[2 * batch + b];
+            rel[b] = denom > 0.0 ? hn[batch + b] / denom : (hn[batch + b] == 0.0 ? 0.0 : INFINITY);
+            if (rel[b] <= refine->tol) {
+                conv[b] = 1;
+                act[b] = 0;
+            } else if (iters[b] >= refine->max_iter) {
+                act[b] = 0;
+            }
+            n_active += act[b];
+        }
+        if (n_active == 0) break;
+        HARP_HIP_CHECK(hipMemcpyAsync(W.active, act.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+        // correction: D = LU^-1 R, X += D
+        if (dtype == HARP_C64) {
+            if ((s = solve_into(W.R, n, mat, W.active, true)) != HARP_OK) return s;
+        } else {
+            if ((s = solve_impl<double>(n, nrhs, batch, static_cast<const double*>(d_LU), lda, stride_lu, d_ipiv,
+                                        reinterpret_cast<double*>(W.R), n, mat, W.active, st)) != HARP_OK)
+                return s;
+            const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
+            hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st,
+                               static_cast<double2*>(d_X), ldx, stride_x, W.R, n, mat, n, nrhs, W.active);
+            HARP_LAUNCH_CHECK();
+        }
+        for (int b = 0; b < batch; ++b) iters[b] += act[b];
+        // make sure the host vectors are not reused before the copies finish
+        HARP_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    bool all = true;
+    for (int b = 0; b < batch; ++b) {
+        if (report) {
+            report[b].iters = iters[b];
+            report[b].converged = conv[b];
+            report[b].resid_rel = rel[b];
+        }
+        all = all && conv[b];
+    }
+    return all ? HARP_OK : HARP_E_NOCONV;
+}
+
+#include "../../include/harp_debug.h"
+
+extern "C" harp_status harp_debug_cgemm(harp_dtype dtype, int32_t M, int32_t N, int32_t K, int32_t batch, double alpha,
+                                        const void* d_A, int64_t lda, int64_t sA, const void* d_B, int64_t ldb,
+                                        int64_t sB, double beta, const void* d_C, int64_t ldc, int64_t sC, void* d_D,
+                                        int64_t ldd, int64_t sD, hipStream_t stream) {
+    if (M < 0 || N < 0 || K < 0 || batch <= 0 || batch > 65535 || !d_D) return HARP_E_ARG;
+    if ((K > 0 && (!d_A || !d_B)) || (beta != 0.0 && !d_C)) return HARP_E_ARG;
+    if (lda < std::max(1, M) || ldb < std::max(1, K) || ldd < std::max(1, M)) return HARP_E_ARG;
+    if (beta != 0.0 && ldc < std::max(1, M)) return HARP_E_ARG;
+    if (dtype == HARP_C64) {
+        GemmArgs<float> g{M, N, K, static_cast<const float*>(d_A), lda, sA, static_cast<const float*>(d_B), ldb, sB,
+                          static_cast<const float*>(d_C), ldc, sC, static_cast<float*>(d_D), ldd, sD,
+                          float(alpha), float(beta), nullptr};
+        return cgemm<float>(g, batch, stream);
+    }
+    if (dtype == HARP_C128) {
+        GemmArgs<double> g{M, N, K, static_cast<const double*>(d_A), lda, sA, static_cast<const double*>(d_B), ldb, sB,
+                           static_cast<const double*>(d_C), ldc, sC, static_cast<double*>(d_D), ldd, sD, alpha, beta,
+                           nullptr};
+        return cgemm<double>(g, batch, stream);
+    }
+    return HARP_E_ARG;
+}

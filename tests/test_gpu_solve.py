@@ -1,0 +1,195 @@
+"""GPU parity of the dense reduced solve: the MFMA complex GEMM, the blocked LU
+with partial pivoting, the triangular solves and the FP64 refinement, through
+the C ABI, against numpy/LAPACK and the FP64 CPU oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fill as ofill, solve as osolve  # noqa: E402
+
+from parity import oracle_models, pack  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+REL_SOLVE = 1e-6      # refined complex64 path vs the FP64 oracle
+REL_PLAIN = 1e-10     # complex128 path vs the FP64 oracle
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1702_03781_amd import api as A
+    return A
+
+
+def _rand(shape, seed, dtype=np.complex128):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+
+
+def _to_cm(api, M, dtype):
+    """numpy (b, r, c) -> batched column-major CUDA tensor."""
+    b, r, c = M.shape
+    T = api.colmajor(b, r, c, dtype, "cuda")
+    T.copy_(torch.from_numpy(M))
+    return T
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(64, 128, 16), (70, 33, 21), (130, 200, 64), (1, 1, 1), (40, 17, 0)])
+def test_cgemm_hook(api, dt, shape):
+    from paper_1702_03781_amd._lib import lib
+    M, N, K = shape
+    batch = 3
+    npdt = np.complex64 if dt == "c64" else np.complex128
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    A = _rand((batch, M, K), 1, npdt)
+    B = _rand((batch, K, N), 2, npdt)
+    C = _rand((batch, M, N), 3, npdt)
+    At, Bt, Ct = _to_cm(api, A, tdt), _to_cm(api, B, tdt), _to_cm(api, C, tdt)
+    Dt = api.colmajor(batch, M, N, tdt, "cuda")
+    for alpha, beta in [(-1.0, 1.0), (1.0, 0.0)]:
+        st = lib().harp_debug_cgemm(0 if dt == "c64" else 1, M, N, K, batch, alpha,
+                                    At.data_ptr(), M, M * K, Bt.data_ptr(), max(K, 1), K * N,
+                                    beta, Ct.data_ptr(), M, M * N, Dt.data_ptr(), M, M * N,
+                                    torch.cuda.current_stream().cuda_stream)
+        assert st == 0
+        torch.cuda.synchronize()
+        ref = beta * C.astype(np.complex128) + alpha * (A.astype(np.complex128) @ B.astype(np.complex128))
+        got = Dt.cpu().numpy()
+        scale = np.abs(ref).max() + 1e-30
+        tol = 1e-5 if dt == "c64" else 1e-13
+        assert np.abs(got - ref).max() <= tol * scale * max(1, np.sqrt(K))
+
+
+@pytest.mark.parametrize("dt,n,batch", [("c128", 70, 2), ("c128", 300, 3), ("c64", 111, 2),
+                                        ("c64", 257, 3), ("c128", 64, 1), ("c64", 1, 2)])
+def test_factor_and_solve_random(api, dt, n, batch):
+    """Diagonally weighted random systems (ragged block sizes): solve vs LAPACK;
+    the complex64 factors with FP64 refinement reach the FP64 solution."""
+    A = _rand((batch, n, n), 10 + n) + 4 * np.sqrt(n) * np.eye(n)[None]
+    Bh = _rand((batch, n, 5), 20 + n)
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    LU = _to_cm(api, A.astype(np.complex64 if dt == "c64" else np.complex128), tdt)
+    ipiv, info = api.reduced_factor(LU)
+    B = _to_cm(api, Bh, torch.complex128)
+    X, _ = api.reduced_solve(LU, ipiv, B)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all()
+    ref = np.linalg.solve(A, Bh)
+    err = np.linalg.norm(X.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= (1e-5 if dt == "c64" else 1e-12), err
+    if dt == "c64":
+        Z64 = _to_cm(api, A, torch.complex128)
+        X2, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-13, max_iter=10)
+        torch.cuda.synchronize()
+        err2 = np.linalg.norm(X2.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err2 <= 1e-11, (err2, rep)
+        assert all(r["converged"] for r in rep)
+
+
+def test_pivots_follow_partial_pivoting(api):
+    """Generic matrix: the pivot sequence is LAPACK's (first max |Re|+|Im|)."""
+    import scipy.linalg
+    n = 200
+    A = _rand((1, n, n), 5)
+    LU = _to_cm(api, A, torch.complex128)
+    ipiv, info = api.reduced_factor(LU)
+    torch.cuda.synchronize()
+    _, piv = scipy.linalg.lu_factor(A[0])
+    assert np.array_equal(ipiv.cpu().numpy()[0], piv)
+    # U (upper triangle) agrees with LAPACK's
+    U = np.triu(LU.cpu().numpy()[0])
+    lu_ref, _ = scipy.linalg.lu_factor(A[0])
+    assert np.abs(U - np.triu(lu_ref)).max() <= 1e-11 * np.abs(lu_ref).max()
+
+
+def test_exact_zero_pivot_sets_info(api):
+    n = 100
+    A = _rand((2, n, n), 7)
+    A[1, :, 37] = 0.0                 # exactly singular: zero column 37
+    LU = _to_cm(api, A, torch.complex128)
+    ipiv, info = api.reduced_factor(LU)
+    torch.cuda.synchronize()
+    assert list(info.cpu().numpy()) == [0, 38]
+
+
+def test_refinement_report_and_noconv(api):
+    n = 96
+    A = _rand((1, n, n), 8) + 3 * np.sqrt(n) * np.eye(n)[None]
+    LU = _to_cm(api, A.astype(np.complex64), torch.complex64)
+    ipiv, _ = api.reduced_factor(LU)
+    B = _to_cm(api, _rand((1, n, 4), 9), torch.complex128)
+    Z64 = _to_cm(api, A, torch.complex128)
+    from paper_1702_03781_amd._lib import HarpError
+    with pytest.raises(HarpError) as e:
+        api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-300, max_iter=0)
+    assert e.value.status == -4
+    X, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-300, max_iter=0, raise_noconv=False)
+    assert rep[0]["iters"] == 0 and not rep[0]["converged"]
+    X, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-12, max_iter=5)
+    assert rep[0]["converged"] and 1 <= rep[0]["iters"] <= 5 and rep[0]["resid_rel"] <= 1e-12
+
+
+def _pipeline(api, models_o, x, y, refined=True):
+    mb = api.stack_models([pack(api, m) for m in models_o])
+    xt = torch.from_numpy(np.asarray(x, np.float64)).cuda()
+    yt = torch.from_numpy(np.asarray(y, np.float64)).cuda()
+    n_ant = len(x)
+    B = api.harp_port_rhs(mb, n_ant)
+    if refined:
+        Z64, Z32, info = api.harp_fill(mb, xt, yt, dtype="c128", dual=True)
+        ipiv, finfo = api.reduced_factor(Z32)
+        X, rep = api.reduced_solve(Z32, ipiv, B, Z64=Z64, tol=1e-10, max_iter=10)
+    else:
+        Z64, _, info = api.harp_fill(mb, xt, yt, dtype="c128")
+        ipiv, finfo = api.reduced_factor(Z64)
+        X, rep = api.reduced_solve(Z64, ipiv, B)
+    Y = api.harp_port_admittance(mb, X)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (finfo.cpu().numpy() == 0).all()
+    return X.cpu().numpy(), Y.cpu().numpy(), rep
+
+
+def _check_against_oracle(wl, models, X, Y, tol):
+    worst = 0.0
+    for f, m in enumerate(models):
+        Zo = ofill.fill(m, wl.x, wl.y)
+        Bo = osolve.port_rhs(m.w, wl.n_ant)
+        Xo = osolve.solve(Zo, Bo)
+        Yo = osolve.admittance(Xo, m.w, wl.n_ant)
+        ex = np.linalg.norm(X[f] - Xo) / np.linalg.norm(Xo)
+        ey = np.linalg.norm(Y[f] - Yo) / np.linalg.norm(Yo)
+        col = (np.linalg.norm(X[f] - Xo, axis=0) / np.linalg.norm(Xo, axis=0)).max()
+        worst = max(worst, ex, ey, col)
+        assert ex <= tol and ey <= tol and col <= tol, (f, ex, ey, col)
+    return worst
+
+
+@pytest.mark.parametrize("refined", [True, False])
+def test_hot_path_cfg1(api, refined):
+    wl, models = oracle_models("cfg1")
+    X, Y, rep = _pipeline(api, models, wl.x, wl.y, refined)
+    _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
+
+
+@pytest.mark.parametrize("refined", [True, False])
+def test_hot_path_cfg2_all_frequencies(api, refined):
+    """The benchmark's configuration: 256 elements x 8 MBFs (n = 2048), 256
+    ports, 16 frequencies in one batch; every frequency vs the oracle."""
+    wl, models = oracle_models("cfg2")
+    X, Y, rep = _pipeline(api, models, wl.x, wl.y, refined)
+    _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
+    if refined:
+        assert all(r["converged"] for r in rep)
+
+
+def test_hot_path_strong_coupling(api):
+    """Larger self-block regularisation: off-diagonal blocks ~ 1/4 of the
+    diagonal, so the solve depends on the coupling (cfg1 element, a_w = 0.3)."""
+    wl, models = oracle_models("cfg1", wire_radius=0.3)
+    for refined in (True, False):
+        X, Y, _ = _pipeline(api, models, wl.x, wl.y, refined)
+        _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
