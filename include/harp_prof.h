@@ -1,0 +1,48 @@
+/*
+ * Kernel-class timers of libharp (instrumentation, not part of the solver's
+ * boundary).  When enabled, every launch of the library's kernels is
+ * bracketed by two HIP events recorded on the launch's own stream, and the
+ * launch's algorithmic work (flops, bytes) is attached to it.  Reading a class
+ * synchronises on its events and returns totals over the launches recorded
+ * since the last harp_prof_enable(1).
+ *
+ * For callers that time whole passes: enable, run, read, disable.  Not for
+ * use under stream capture; not thread-safe (one profiling thread).
+ *
+ * Algorithmic work per launch: complex GEMM 8 M N K flops (per matrix of the
+ * batch that is active); fill 8 / 16 / 24 bytes written per entry (complex64
+ * / complex128 / both) and 0 flops (its flops, (2P+1)(2Q+4) * 2 per
+ * model-evaluated entry, depend on each model's order, which the caller
+ * knows); other classes report 0.
+ */
+#ifndef HARP_PROF_H
+#define HARP_PROF_H
+
+#include "harp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HARP_K_FILL = 0,      /* harp_fill kernels */
+    HARP_K_GETF2 = 1,     /* pivoting panel factorisation */
+    HARP_K_TRSM_L = 2,    /* row exchanges + unit-lower block solve */
+    HARP_K_TRSM_U = 3,    /* upper block solve */
+    HARP_K_GEMM32 = 4,    /* complex64 MFMA GEMM */
+    HARP_K_GEMM64 = 5,    /* complex128 MFMA GEMM */
+    HARP_K_AUX = 6,       /* conversions, norms, axpy, ports, info reset */
+    HARP_K_COUNT = 7
+} harp_kernel_class;
+
+/* on != 0: clear the records and start recording; on == 0: stop. */
+harp_status harp_prof_enable(int32_t on);
+
+/* Totals of one class: launches, summed event time (ms), flops, bytes. */
+harp_status harp_prof_read(int32_t cls, int64_t *launches, double *ms, double *flops, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HARP_PROF_H */

@@ -59,8 +59,12 @@ SIGNATURES = {
 }
 
 
-# test hook declared in include/harp_debug.h (not part of the boundary)
+# test hook (include/harp_debug.h) and kernel-class timers
+# (include/harp_prof.h); neither is part of the solver boundary
 DEBUG_SIGNATURES = {
+    "harp_prof_enable": (c_i32, [c_i32]),
+    "harp_prof_read": (c_i32, [c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
+                               ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
     "harp_debug_cgemm": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_vp, c_i64, c_i64, c_vp,
                                  c_i64, c_i64, c_dbl, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
 }

@@ -348,3 +348,92 @@ __all__ = [
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid",
 ]
+
+
+# --------------------------------------------------------------------------
+# whole hot path with preallocated buffers
+# --------------------------------------------------------------------------
+
+class StationSolver:
+    """Fill, factor, port excitation, solve and admittances for a batch of
+    frequencies of one layout, with every device buffer allocated once.
+
+    mode "refined": FP64 fill written as complex128 (residual matrix) and as
+    its complex64 rounding (factored on the matrix cores), complex64 solve,
+    FP64 iterative refinement to `tol`.
+    mode "plain": complex128 fill, factor and solve (the FP64 reference path).
+    """
+
+    def __init__(self, models: ModelBatch, x: torch.Tensor, y: torch.Tensor, mode="refined",
+                 tol: float = 1e-10, max_iter: int = 10):
+        self.models, self.mode, self.tol, self.max_iter = models, mode, tol, max_iter
+        dev = models.data.device
+        self.x = x.contiguous()
+        self.y = y.contiguous()
+        self.n_ant = int(x.numel())
+        n = self.n = self.n_ant * models.n_mbf
+        nf = models.n_freq
+        self.Z64 = colmajor(nf, n, n, torch.complex128, dev)
+        self.Z32 = colmajor(nf, n, n, torch.complex64, dev) if mode == "refined" else None
+        self.B = colmajor(nf, n, self.n_ant, torch.complex128, dev)
+        self.X = colmajor(nf, n, self.n_ant, torch.complex128, dev)
+        self.Y = colmajor(nf, self.n_ant, self.n_ant, torch.complex128, dev)
+        self.info = torch.empty(nf, dtype=torch.int32, device=dev)
+        self.finfo = torch.empty(nf, dtype=torch.int32, device=dev)
+        self.ipiv = torch.empty((nf, n), dtype=torch.int32, device=dev)
+        dt = C64 if mode == "refined" else C128
+        ws_b = ctypes.c_size_t()
+        check(lib().reduced_solve_ws(n, self.n_ant, nf, dt, int(mode == "refined"),
+                                     ctypes.byref(ws_b)), "reduced_solve_ws")
+        self.ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=dev)
+        self.ws_bytes = ws_b.value
+        self.reports = None
+
+    def step(self):
+        L = lib()
+        mb, n, na, nf = self.models, self.n, self.n_ant, self.models.n_freq
+        st = _stream(mb.data.device)
+        refined = self.mode == "refined"
+        pz, ldz, sz = _cm(self.Z64, "Z64")
+        p32, ld32, s32 = _cm(self.Z32, "Z32") if refined else (0, 0, 0)
+        check(L.harp_fill(_ptr(mb.data), mb.stride, nf, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
+                          _ptr(self.y), na, 0.0, C128, pz, ldz, sz, p32, ld32, s32,
+                          _ptr(self.info), st), "harp_fill")
+        pb, ldb, sb = _cm(self.B, "B")
+        check(L.harp_port_rhs(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, pb, ldb, sb, st),
+              "harp_port_rhs")
+        pf, ldf, sf = (p32, ld32, s32) if refined else (pz, ldz, sz)
+        dt = C64 if refined else C128
+        check(L.reduced_factor(n, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.finfo), None, 0,
+                               st), "reduced_factor")
+        px, ldx, sx = _cm(self.X, "X")
+        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter)) if refined else None
+        rep = (HarpRefineReport * nf)() if refined else None
+        check(L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), pb, ldb, sb, px, ldx,
+                              sx, ctypes.byref(ref) if ref is not None else None, rep,
+                              _ptr(self.ws), self.ws_bytes, st), "reduced_solve")
+        py, ldy, sy = _cm(self.Y, "Y")
+        check(L.harp_port_admittance(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, px, ldx, sx, py,
+                                     ldy, sy, st), "harp_port_admittance")
+        if rep is not None:
+            self.reports = [{"iters": r.iters, "converged": bool(r.converged),
+                             "resid_rel": r.resid_rel} for r in rep]
+        return self.X, self.Y
+
+
+def prof_enable(on: bool) -> None:
+    check(lib().harp_prof_enable(1 if on else 0), "harp_prof_enable")
+
+
+PROF_CLASSES = ["fill", "getf2", "trsm_lower", "trsm_upper", "gemm_c64", "gemm_c128", "aux"]
+
+
+def prof_read() -> dict:
+    out = {}
+    for i, name in enumerate(PROF_CLASSES):
+        n = ctypes.c_int64()
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().harp_prof_read(i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                   ctypes.byref(by)), "harp_prof_read")
+        out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out

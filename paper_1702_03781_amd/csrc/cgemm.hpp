@@ -26,6 +26,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace harp {
 
@@ -124,20 +125,36 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
         for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_c][b_k + e] = rb[e];
     };
 
+    // accumulators start at beta * C (read before the K loop so its latency
+    // overlaps the first A/B chunk); alpha is folded into the A operand
+    const int b_col = lane & 15;
+    const int M2 = 2 * g.M;
     acc_t acc[RB][CB];
+    {
+        const T* Cr = g.C ? g.C + 2 * size_t(bz) * g.sC : nullptr;
 #pragma unroll
-    for (int i = 0; i < RB; ++i)
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int j = 0; j < CB; ++j) acc[i][j] = acc_t{T(0), T(0), T(0), T(0)};
+            for (int j = 0; j < CB; ++j) {
+                const int col = col0 + wc + j * 16 + b_col;
+                const int rbase = 2 * (row0 + wr + i * 8);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = rbase + Mfma<T>::out_row(lane, v);
+                    acc[i][j][v] = (g.beta != T(0) && col < g.N && rr < M2)
+                                       ? g.beta * Cr[2 * size_t(col) * g.ldc + rr]
+                                       : T(0);
+                }
+            }
+    }
 
     // operand selection for this lane (see the header comment)
     const int s = lane & 1;                  // real row parity: 0 = re row, 1 = im row
     const int u = (lane >> 4) & 1;           // real k parity:   0 = re k,   1 = im k
     const int kq = lane >> 5;                // which of the 2 complex k of an MFMA step
     const bool take_im_a = (s ^ u) != 0;
-    const T sign_a = (s == 0 && u == 1) ? T(-1) : T(1);
+    const T sign_a = ((s == 0 && u == 1) ? T(-1) : T(1)) * g.alpha;
     const int a_row = (lane & 15) >> 1;      // complex row within an 8-row block
-    const int b_col = lane & 15;
 
     const int nchunks = (g.K + BK - 1) / BK;
     load_chunk(0);
@@ -170,10 +187,8 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
     }
 
     // epilogue in the real view of the interleaved storage: real row 2i + part
-    // is exactly the MFMA output row, and alpha, beta are real
-    const T* Cr = g.C ? g.C + 2 * size_t(bz) * g.sC : nullptr;
+    // is exactly the MFMA output row
     T* Dr = g.D + 2 * size_t(bz) * g.sD;
-    const int M2 = 2 * g.M;
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
 #pragma unroll
@@ -184,10 +199,7 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = rbase + Mfma<T>::out_row(lane, v);
-                if (rr >= M2) continue;
-                T val = g.alpha * acc[i][j][v];
-                if (g.beta != T(0)) val += g.beta * Cr[2 * size_t(col) * g.ldc + rr];
-                Dr[2 * size_t(col) * g.ldd + rr] = val;
+                if (rr < M2) Dr[2 * size_t(col) * g.ldd + rr] = acc[i][j][v];
             }
         }
     }
@@ -195,21 +207,26 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
 
 template <typename T> struct GemmTile;
 template <> struct GemmTile<float> {
-    static constexpr int BM = 64, BN = 128, BK = 16;
+    static constexpr int BM = 64, BN = 64, BK = 16;
 };
 template <> struct GemmTile<double> {
-    static constexpr int BM = 64, BN = 64, BK = 16;
+    static constexpr int BM = 32, BN = 64, BK = 16;
 };
 
 // Enqueue D = beta C + alpha A B for `batch` matrices.  M, N, K may be zero.
+// eff_batch (< 0: batch) is the number of matrices not skipped by g.active,
+// used only for the work accounting of the profiler.
 template <typename T>
-inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream) {
+inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
     if (g.M <= 0 || g.N <= 0 || batch <= 0) return HARP_OK;
     constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN, BK = GemmTile<T>::BK;
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     // K == 0 runs the same kernel with an empty contraction: D = beta C
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK>), dim3(unsigned(tiles), 1u, unsigned(batch)), dim3(256), 0,
-                       stream, g);
+    const double nb = double(eff_batch < 0 ? batch : eff_batch);
+    HARP_PROF_LAUNCH(sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64, stream,
+                     8.0 * double(g.M) * double(g.N) * double(g.K) * nb, 0.0,
+                     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK>), dim3(unsigned(tiles), 1u, unsigned(batch)),
+                                        dim3(256), 0, stream, g));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }

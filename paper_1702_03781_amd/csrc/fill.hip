@@ -26,6 +26,7 @@
 #include <math.h>
 
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace harp {
 namespace {
@@ -216,8 +217,11 @@ harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
     switch (a.Q) {
 #define HARP_FILL_CASE(QQ)                                                                 \
     case QQ:                                                                               \
-        hipLaunchKernelGGL((fill_kernel<R, QQ, DUAL>), grid, dim3(256), 0, stream, a,      \
-                           a.models, a.x, a.y, a.Z, a.Z32);                                \
+        HARP_PROF_LAUNCH(HARP_K_FILL, stream, 0.0,                                         \
+                         double(a.n_freq) * double(a.n_ant) * a.n_mbf * double(a.n_ant) * \
+                             a.n_mbf * (DUAL ? 24.0 : double(2 * sizeof(R))),              \
+                         hipLaunchKernelGGL((fill_kernel<R, QQ, DUAL>), grid, dim3(256), 0,\
+                                            stream, a, a.models, a.x, a.y, a.Z, a.Z32));   \
         break;
         HARP_FILL_CASE(2)
         HARP_FILL_CASE(3)
@@ -274,7 +278,9 @@ extern "C" harp_status harp_fill(const void* d_models, int64_t model_stride, int
     a.ld32 = ld32;
     a.stride32 = stride32;
     a.info = d_info;
-    hipLaunchKernelGGL(fill_info_init, dim3((n_freq + 255) / 256), dim3(256), 0, stream, d_info, n_freq);
+    HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
+                     hipLaunchKernelGGL(fill_info_init, dim3((n_freq + 255) / 256), dim3(256), 0, stream, d_info,
+                                        n_freq));
     HARP_LAUNCH_CHECK();
     const int tiles = ((n_ant + kTileM - 1) / kTileM) * ((n_ant + kTileN - 1) / kTileN);
     const dim3 grid{unsigned(tiles), unsigned(n_freq), 1u};

@@ -30,6 +30,7 @@
 
 #include "cgemm.hpp"
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace harp {
 namespace {
@@ -69,6 +70,55 @@ struct PanelArgs {
     int32_t* info;      // [batch]
 };
 
+// widest outer block the panel kernel serves (its LDS staging is sized for it)
+constexpr int NBMAX = 64;
+
+// Wave-wide argmax of (value, row) with the LAPACK tie rule (larger value,
+// then smaller row).  DPP moves inside each 16-lane row (quad swaps, then
+// rotations by 4 and 8), then the four row results are read as scalars.
+// A NaN value never wins a comparison.
+template <int CTRL> __device__ inline int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ inline float dpp_v(float v) { return __int_as_float(dpp_i<CTRL>(__float_as_int(v))); }
+template <int CTRL> __device__ inline double dpp_v(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL>(int(b)), hi = dpp_i<CTRL>(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ inline float readlane_v(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double readlane_v(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b), l), hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <typename T> __device__ inline void take_if_better(T ov, int oi, T& best, int& bidx) {
+    if (ov > best || (ov == best && oi < bidx)) {
+        best = ov;
+        bidx = oi;
+    }
+}
+template <typename T, int CTRL> __device__ inline void dpp_step(T& best, int& bidx) {
+    take_if_better(dpp_v<CTRL>(best), dpp_i<CTRL>(bidx), best, bidx);
+}
+template <typename T> __device__ inline void wave_argmax(T& best, int& bidx) {
+    dpp_step<T, 0xB1>(best, bidx);    // quad_perm [1,0,3,2]
+    dpp_step<T, 0x4E>(best, bidx);    // quad_perm [2,3,0,1]
+    dpp_step<T, 0x124>(best, bidx);   // row_ror:4
+    dpp_step<T, 0x128>(best, bidx);   // row_ror:8
+    T b = readlane_v(best, 0);
+    int i = __builtin_amdgcn_readlane(bidx, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) take_if_better(readlane_v(best, r), __builtin_amdgcn_readlane(bidx, r), b, i);
+    best = b;
+    bidx = i;
+}
+
+// One workgroup per matrix factors rows [j0, n) x columns [j0, j0+w) held in
+// registers (thread t owns rows j0 + t + r NT).  One barrier per column: each
+// wave publishes its best candidate together with that row, and the owner of
+// row j publishes row j; after the barrier every thread picks the winner,
+// the two owners exchange rows, and all threads scale and update.
 template <typename T, int NT, int RPT, int W>
 __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     using V = typename C2<T>::t;
@@ -79,12 +129,14 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     const int n = pa.n, j0 = pa.j0, w = pa.w;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    __shared__ T red_v[2][NW];
-    __shared__ int red_i[2][NW];
-    __shared__ V prow[2][W];
+    __shared__ T cand_v[2][NW];
+    __shared__ int cand_i[2][NW];
+    __shared__ V cand_row[2][NW][W];
     __shared__ V jrow[2][W];
     __shared__ V Ls[W][W];
     __shared__ int piv_s[W];
+    __shared__ int cand_s[2 * W], src_s[2 * W];
+    __shared__ V stage[NBMAX - W][2 * W];
 
     V a[RPT][W];
 #pragma unroll
@@ -100,102 +152,74 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
         if (jj >= w) break;
         const int par = jj & 1;
         const int j = j0 + jj;
-        // local candidate: first row maximising |re| + |im| among rows >= j
-        // best = -1 with the diagonal row as default keeps p inside [j, n) even
-        // when the column holds NaN
         T best = T(-1);
         int bidx = j;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int row = j0 + tid + r * NT;
-            const V v = a[r][jj];
-            const T m = fabs(v.x) + fabs(v.y);
-            if (row >= j && row < n && (m > best || (m == best && row < bidx))) {
-                best = m;
-                bidx = row;
-            }
+            const T m = fabs(a[r][jj].x) + fabs(a[r][jj].y);
+            if (row >= j && row < n) take_if_better(m, row, best, bidx);
         }
+        wave_argmax(best, bidx);
+        // the owner of the wave's best row publishes it; the owner of row j publishes row j
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const T ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bidx, off, 64);
-            if (ob > best || (ob == best && oi < bidx)) {
-                best = ob;
-                bidx = oi;
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            if (row == bidx) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) cand_row[par][wave][c] = a[r][c];
+            }
+            if (row == j) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) jrow[par][c] = a[r][c];
             }
         }
         if (lane == 0) {
-            red_v[par][wave] = best;
-            red_i[par][wave] = bidx;
+            cand_v[par][wave] = best;
+            cand_i[par][wave] = bidx;
         }
         __syncthreads();
-        best = red_v[par][0];
-        bidx = red_i[par][0];
+        int wb = 0;
+        best = cand_v[par][0];
+        bidx = cand_i[par][0];
 #pragma unroll
         for (int q = 1; q < NW; ++q) {
-            const T ob = red_v[par][q];
-            const int oi = red_i[par][q];
+            const T ob = cand_v[par][q];
+            const int oi = cand_i[par][q];
             if (ob > best || (ob == best && oi < bidx)) {
                 best = ob;
                 bidx = oi;
+                wb = q;
             }
         }
         const int p = bidx;
-        const int own_p = (p - j0) % NT, slot_p = (p - j0) / NT;
-        const int own_j = (j - j0) % NT, slot_j = (j - j0) / NT;
-        if (tid == own_p) {
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (r == slot_p)
-#pragma unroll
-                    for (int c = 0; c < W; ++c) prow[par][c] = a[r][c];
-        }
-        if (tid == own_j) {
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (r == slot_j)
-#pragma unroll
-                    for (int c = 0; c < W; ++c) jrow[par][c] = a[r][c];
-        }
         if (tid == 0) {
             piv_s[jj] = p;
             pa.ipiv[size_t(b) * n + j] = p;
             if (best == T(0)) atomicCAS(pa.info + b, 0, j + 1);
         }
-        __syncthreads();
-        // exchange rows j and p
-        if (p != j) {
-            if (tid == own_j) {
-#pragma unroll
-                for (int r = 0; r < RPT; ++r)
-                    if (r == slot_j)
-#pragma unroll
-                        for (int c = 0; c < W; ++c) a[r][c] = prow[par][c];
-            }
-            if (tid == own_p) {
-#pragma unroll
-                for (int r = 0; r < RPT; ++r)
-                    if (r == slot_p)
-#pragma unroll
-                        for (int c = 0; c < W; ++c) a[r][c] = jrow[par][c];
-            }
-        }
-        // scale the column below the pivot and update the rest of the panel
-        const V piv = prow[par][jj];
         const bool nz = best != T(0);
-        const V inv = nz ? crecip(piv) : V{T(0), T(0)};
+        const V inv = nz ? crecip(cand_row[par][wb][jj]) : V{T(0), T(0)};
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int row = j0 + tid + r * NT;
+            if (p != j && row == j) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[r][c] = cand_row[par][wb][c];
+            } else if (p != j && row == p) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[r][c] = jrow[par][c];
+            }
             if (row > j && row < n && nz) {
                 const V l = cm(a[r][jj], inv);
                 a[r][jj] = l;
 #pragma unroll
                 for (int c = jj + 1; c < W; ++c)
-                    if (c < w) a[r][c] = cfms(a[r][c], l, prow[par][c]);
+                    if (c < w) a[r][c] = cfms(a[r][c], l, cand_row[par][wb][c]);
             }
         }
     }
+    __syncthreads();
 
     // write the panel back; keep its unit-lower top block in LDS
 #pragma unroll
@@ -211,35 +235,53 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
             for (int c = 0; c < W; ++c) Ls[tid][c] = a[0][c];
         }
     }
+    // rows touched by this panel's exchanges: the w top rows and the w pivot
+    // rows; source of each after all exchanges, by walking them backwards
+    if (tid < 2 * w) {
+        const int r = tid < w ? j0 + tid : piv_s[tid - w];
+        int src = r;
+        for (int q = w - 1; q >= 0; --q) {
+            if (src == j0 + q) src = piv_s[q];
+            else if (src == piv_s[q]) src = j0 + q;
+        }
+        cand_s[tid] = r;
+        src_s[tid] = src;
+    }
     __syncthreads();
 
-    // other columns of the outer block: row exchanges of this panel, then the
-    // unit-lower solve for the columns right of the panel
+    // other columns of the outer block: gather the exchanged rows through LDS
     const int left = j0 - pa.k0;
     const int right = pa.kend - (j0 + w);
-    for (int e = tid; e < left + right; e += NT) {
-        const int col = e < left ? pa.k0 + e : j0 + w + (e - left);
-        V* Ac = A + size_t(col) * lda;
-        for (int q = 0; q < w; ++q) {
-            const int pr = piv_s[q];
-            if (pr != j0 + q) {
-                const V t0 = Ac[j0 + q];
-                Ac[j0 + q] = Ac[pr];
-                Ac[pr] = t0;
-            }
-        }
-        if (e >= left) {
-            V x[W];
+    const int nother = left + right;
+    const int n2 = 2 * w;
+    for (int e = tid; e < n2 * nother; e += NT) {
+        const int t = e % n2, oc = e / n2;
+        const int col = oc < left ? pa.k0 + oc : j0 + w + (oc - left);
+        stage[oc][t] = A[size_t(col) * lda + src_s[t]];
+    }
+    __syncthreads();
+    for (int e = tid; e < n2 * nother; e += NT) {
+        const int t = e % n2, oc = e / n2;
+        const bool is_right = oc >= left;
+        const int col = is_right ? j0 + w + (oc - left) : pa.k0 + oc;
+        const int r = cand_s[t];
+        // right columns: the top rows are rewritten by the solve below
+        if (is_right && r < j0 + w) continue;
+        A[size_t(col) * lda + r] = stage[oc][t];
+    }
+    // unit-lower solve of the top rows of the right columns
+    for (int oc = left + tid; oc < nother; oc += NT) {
+        const int col = j0 + w + (oc - left);
+        V x[W];
 #pragma unroll
-            for (int i = 0; i < W; ++i) x[i] = i < w ? Ac[j0 + i] : V{T(0), T(0)};
+        for (int i = 0; i < W; ++i) x[i] = i < w ? stage[oc][i] : V{T(0), T(0)};
 #pragma unroll
-            for (int i = 1; i < W; ++i)
+        for (int i = 1; i < W; ++i)
 #pragma unroll
-                for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[i][q], x[q]);
+            for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[i][q], x[q]);
 #pragma unroll
-            for (int i = 0; i < W; ++i)
-                if (i < w) Ac[j0 + i] = x[i];
-        }
+        for (int i = 0; i < W; ++i)
+            if (i < w) A[size_t(col) * lda + j0 + i] = x[i];
     }
 }
 
@@ -259,109 +301,154 @@ struct TrsmArgs {
     const int32_t* active;
 };
 
-// The solves work on 16-row chunks: a chunk is loaded, updated with the
-// already final chunks (re-read from memory, L1-resident), solved in
-// registers and stored, so each thread holds at most two chunks.
+// Block-row solves on CB columns per 256-thread workgroup.  The block row
+// (and, for the lower solve, the rows its exchanges displace) is gathered into
+// LDS, solved there in 16-row chunks (a chunk's diagonal solve by one thread
+// per column, the update of the later chunks by all threads), and written
+// back with coalesced stores.
 constexpr int kCh = 16;
 
+template <typename T> struct TrsmCols;
+template <> struct TrsmCols<float> { static constexpr int CB = 64; };
+template <> struct TrsmCols<double> { static constexpr int CB = 32; };
+
 template <typename T, int NB>
-__global__ void __launch_bounds__(64) laswp_trsm_lower_kernel(TrsmArgs ta) {
+__global__ void __launch_bounds__(256) laswp_trsm_lower_kernel(TrsmArgs ta) {
     using V = typename C2<T>::t;
+    constexpr int CB = TrsmCols<T>::CB;
     static_assert(NB % kCh == 0, "block size");
     const int b = blockIdx.y;
     if (ta.active && ta.active[b] == 0) return;
     const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
     V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
     const int32_t* ipiv = ta.ipiv + size_t(b) * ta.n;
-    const int k0 = ta.k0, nbo = ta.nbo;
+    const int k0 = ta.k0, nbo = ta.nbo, tid = threadIdx.x;
+    const int c0 = ta.c_begin + blockIdx.x * CB;
+    const int ncols = min(CB, ta.c_end - c0);
     __shared__ V Ls[NB][NB + 1];
-    __shared__ int pv[NB];
-    for (int e = threadIdx.x; e < NB * NB; e += 64) {
+    __shared__ V S[CB][2 * NB + 1];
+    __shared__ int pv[NB], cand[2 * NB], src[2 * NB];
+    for (int e = tid; e < NB * NB; e += 256) {
         const int i = e % NB, j = e / NB;
-        Ls[i][j] = (i < nbo && j < nbo) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+        Ls[i][j] = (i < nbo && j < nbo && i > j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
     }
-    for (int e = threadIdx.x; e < nbo; e += 64) pv[e] = ipiv[k0 + e];
+    for (int e = tid; e < nbo; e += 256) pv[e] = ipiv[k0 + e];
     __syncthreads();
-    const int col = ta.c_begin + blockIdx.x * 64 + threadIdx.x;
-    if (col >= ta.c_end) return;
-    V* Xc = X + size_t(col) * ta.ldx + k0;
-    for (int q = 0; q < nbo; ++q) {
-        const int pr = pv[q] - k0;
-        if (pr != q) {
-            const V t0 = Xc[q];
-            Xc[q] = Xc[pr];
-            Xc[pr] = t0;
+    const int n2 = 2 * nbo;
+    if (tid < n2) {
+        const int r = tid < nbo ? k0 + tid : pv[tid - nbo];
+        int sr = r;
+        for (int q = nbo - 1; q >= 0; --q) {
+            if (sr == k0 + q) sr = pv[q];
+            else if (sr == pv[q]) sr = k0 + q;
         }
+        cand[tid] = r;
+        src[tid] = sr;
     }
+    __syncthreads();
+    for (int e = tid; e < n2 * ncols; e += 256) {
+        const int t = e % n2, c = e / n2;
+        S[c][t] = X[size_t(c0 + c) * ta.ldx + src[t]];
+    }
+    __syncthreads();
+    // rows displaced below the block row
+    for (int e = tid; e < nbo * ncols; e += 256) {
+        const int t = nbo + e % nbo, c = e / nbo;
+        const int r = cand[t];
+        if (r >= k0 + nbo) X[size_t(c0 + c) * ta.ldx + r] = S[c][t];
+    }
+    // forward substitution with the unit-lower diagonal block
     const int nch = (nbo + kCh - 1) / kCh;
-    for (int c = 0; c < nch; ++c) {
-        V x[kCh];
+    for (int q = 0; q < nch; ++q) {
+        if (tid < ncols) {
+            V x[kCh];
 #pragma unroll
-        for (int i = 0; i < kCh; ++i) x[i] = (c * kCh + i < nbo) ? Xc[c * kCh + i] : V{T(0), T(0)};
-        for (int p = 0; p < c; ++p) {
-            V y[kCh];
+            for (int i = 0; i < kCh; ++i) x[i] = S[tid][q * kCh + i];
 #pragma unroll
-            for (int q = 0; q < kCh; ++q) y[q] = Xc[p * kCh + q];
+            for (int i = 1; i < kCh; ++i)
 #pragma unroll
-            for (int i = 0; i < kCh; ++i)
+                for (int j = 0; j < i; ++j) x[i] = cfms(x[i], Ls[q * kCh + i][q * kCh + j], x[j]);
 #pragma unroll
-                for (int q = 0; q < kCh; ++q) x[i] = cfms(x[i], Ls[c * kCh + i][p * kCh + q], y[q]);
+            for (int i = 0; i < kCh; ++i) S[tid][q * kCh + i] = x[i];
         }
+        __syncthreads();
+        const int rows_below = nbo - (q + 1) * kCh;
+        if (rows_below > 0) {
+            for (int e = tid; e < rows_below * ncols; e += 256) {
+                const int i = (q + 1) * kCh + e % rows_below, c = e / rows_below;
+                V acc = S[c][i];
 #pragma unroll
-        for (int i = 1; i < kCh; ++i)
-#pragma unroll
-            for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[c * kCh + i][c * kCh + q], x[q]);
-#pragma unroll
-        for (int i = 0; i < kCh; ++i)
-            if (c * kCh + i < nbo) Xc[c * kCh + i] = x[i];
+                for (int j = 0; j < kCh; ++j) acc = cfms(acc, Ls[i][q * kCh + j], S[c][q * kCh + j]);
+                S[c][i] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nbo * ncols; e += 256) {
+        const int i = e % nbo, c = e / nbo;
+        X[size_t(c0 + c) * ta.ldx + k0 + i] = S[c][i];
     }
 }
 
 // upper solve with the non-unit diagonal block U11 (backward substitution)
 template <typename T, int NB>
-__global__ void __launch_bounds__(64) trsm_upper_kernel(TrsmArgs ta) {
+__global__ void __launch_bounds__(256) trsm_upper_kernel(TrsmArgs ta) {
     using V = typename C2<T>::t;
+    constexpr int CB = TrsmCols<T>::CB;
     static_assert(NB % kCh == 0, "block size");
     const int b = blockIdx.y;
     if (ta.active && ta.active[b] == 0) return;
     const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
     V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
-    const int k0 = ta.k0, nbo = ta.nbo;
+    const int k0 = ta.k0, nbo = ta.nbo, tid = threadIdx.x;
+    const int c0 = ta.c_begin + blockIdx.x * CB;
+    const int ncols = min(CB, ta.c_end - c0);
     __shared__ V Us[NB][NB + 1];
+    __shared__ V S[CB][NB + 1];
     __shared__ V dinv[NB];
-    for (int e = threadIdx.x; e < NB * NB; e += 64) {
+    for (int e = tid; e < NB * NB; e += 256) {
         const int i = e % NB, j = e / NB;
-        Us[i][j] = (i < nbo && j < nbo) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+        Us[i][j] = (i < nbo && j < nbo && i <= j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+    }
+    for (int e = tid; e < nbo * ncols; e += 256) {
+        const int i = e % nbo, c = e / nbo;
+        S[c][i] = X[size_t(c0 + c) * ta.ldx + k0 + i];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < NB; e += 64) dinv[e] = e < nbo ? crecip(Us[e][e]) : V{T(0), T(0)};
+    for (int e = tid; e < NB; e += 256) dinv[e] = e < nbo ? crecip(Us[e][e]) : V{T(0), T(0)};
     __syncthreads();
-    const int col = ta.c_begin + blockIdx.x * 64 + threadIdx.x;
-    if (col >= ta.c_end) return;
-    V* Xc = X + size_t(col) * ta.ldx + k0;
     const int nch = (nbo + kCh - 1) / kCh;
-    for (int c = nch - 1; c >= 0; --c) {
-        V x[kCh];
+    for (int q = nch - 1; q >= 0; --q) {
+        const int hi = min(kCh, nbo - q * kCh);    // rows in this chunk
+        if (tid < ncols) {
+            V x[kCh];
 #pragma unroll
-        for (int i = 0; i < kCh; ++i) x[i] = (c * kCh + i < nbo) ? Xc[c * kCh + i] : V{T(0), T(0)};
-        for (int p = c + 1; p < nch; ++p) {
-            V y[kCh];
+            for (int i = 0; i < kCh; ++i) x[i] = i < hi ? S[tid][q * kCh + i] : V{T(0), T(0)};
 #pragma unroll
-            for (int q = 0; q < kCh; ++q) y[q] = (p * kCh + q < nbo) ? Xc[p * kCh + q] : V{T(0), T(0)};
+            for (int i = kCh - 1; i >= 0; --i) {
+#pragma unroll
+                for (int j = i + 1; j < kCh; ++j) x[i] = cfms(x[i], Us[q * kCh + i][q * kCh + j], x[j]);
+                x[i] = i < hi ? cm(x[i], dinv[q * kCh + i]) : V{T(0), T(0)};
+            }
 #pragma unroll
             for (int i = 0; i < kCh; ++i)
-#pragma unroll
-                for (int q = 0; q < kCh; ++q) x[i] = cfms(x[i], Us[c * kCh + i][p * kCh + q], y[q]);
+                if (i < hi) S[tid][q * kCh + i] = x[i];
         }
-#pragma unroll
-        for (int i = kCh - 1; i >= 0; --i) {
-#pragma unroll
-            for (int q = i + 1; q < kCh; ++q) x[i] = cfms(x[i], Us[c * kCh + i][c * kCh + q], x[q]);
-            x[i] = cm(x[i], dinv[c * kCh + i]);
+        __syncthreads();
+        const int rows_above = q * kCh;
+        if (rows_above > 0) {
+            for (int e = tid; e < rows_above * ncols; e += 256) {
+                const int i = e % rows_above, c = e / rows_above;
+                V acc = S[c][i];
+                for (int j = 0; j < hi; ++j) acc = cfms(acc, Us[i][q * kCh + j], S[c][q * kCh + j]);
+                S[c][i] = acc;
+            }
         }
-#pragma unroll
-        for (int i = 0; i < kCh; ++i)
-            if (c * kCh + i < nbo) Xc[c * kCh + i] = x[i];
+        __syncthreads();
+    }
+    for (int e = tid; e < nbo * ncols; e += 256) {
+        const int i = e % nbo, c = e / nbo;
+        X[size_t(c0 + c) * ta.ldx + k0 + i] = S[c][i];
     }
 }
 
@@ -449,35 +536,44 @@ template <typename T> struct LuCfg {
 };
 
 // Panel width: the register-resident panel holds RPT x W complex values per
-// thread; W shrinks as the matrix grows so the panel stays in registers.
+// thread (8 rows per thread); W shrinks as the matrix grows so the panel stays
+// in registers at the thread count the height needs.
 template <typename T> inline int panel_width(int n) {
-    const int base = sizeof(T) == 4 ? 16 : 8;
-    return n <= 2048 ? base : (n <= 4096 ? base / 2 : base / 4);
+    if (sizeof(T) == 4) return n <= 4096 ? 8 : 4;
+    return n <= 2048 ? 8 : (n <= 4096 ? 4 : 2);
+}
+
+// true when a panel of 8 rows x W complex values per thread fits the VGPR
+// budget of an NT-thread workgroup (512 / (NT / 256) per lane, minus headroom)
+template <typename T, int NT, int W> constexpr bool panel_fits() {
+    return 8 * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
+}
+
+template <typename T, int NT, int W>
+harp_status launch_getf2_nt(const PanelArgs& pa, int batch, hipStream_t st) {
+    if constexpr (panel_fits<T, NT, W>()) {
+        HARP_PROF_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0,
+                         hipLaunchKernelGGL((getf2_kernel<T, NT, 8, W>), dim3(batch), dim3(NT), 0, st, pa));
+        HARP_LAUNCH_CHECK();
+        return HARP_OK;
+    }
+    return HARP_E_ARG;
 }
 
 template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
-    constexpr int W8 = W > 8 ? 8 : W, W4 = W > 4 ? 4 : W;
-    if ((m > 512 * 4 && pa.w > W8) || (m > 512 * 8 && pa.w > W4)) return HARP_E_ARG;
-    if (m <= 512 * 4) {
-        hipLaunchKernelGGL((getf2_kernel<T, 512, 4, W>), dim3(batch), dim3(512), 0, st, pa);
-    } else if (m <= 512 * 8) {
-        hipLaunchKernelGGL((getf2_kernel<T, 512, 8, W8>), dim3(batch), dim3(512), 0, st, pa);
-    } else if (m <= 1024 * 8) {
-        hipLaunchKernelGGL((getf2_kernel<T, 1024, 8, W4>), dim3(batch), dim3(1024), 0, st, pa);
-    } else {
-        return HARP_E_ARG;
-    }
-    HARP_LAUNCH_CHECK();
-    return HARP_OK;
+    if (pa.w > W) return HARP_E_ARG;
+    if (m <= 256 * 8) return launch_getf2_nt<T, 256, W>(pa, batch, st);
+    if (m <= 512 * 8) return launch_getf2_nt<T, 512, W>(pa, batch, st);
+    if (m <= 1024 * 8) return launch_getf2_nt<T, 1024, W>(pa, batch, st);
+    return HARP_E_ARG;
 }
 
 template <typename T>
 harp_status launch_getf2(const PanelArgs& pa, int W, int batch, hipStream_t st) {
     if (pa.w > W) return HARP_E_ARG;
     switch (W) {
-        case 16: return launch_getf2_w<T, 16>(pa, batch, st);
         case 8: return launch_getf2_w<T, 8>(pa, batch, st);
         case 4: return launch_getf2_w<T, 4>(pa, batch, st);
         case 2: return launch_getf2_w<T, 2>(pa, batch, st);
@@ -515,7 +611,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                         hipStream_t st) {
     constexpr int NB = LuCfg<T>::NB;
     const int W = panel_width<T>(n);
-    hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch);
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch));
     HARP_LAUNCH_CHECK();
     harp_status s;
     for (int k0 = 0; k0 < n; k0 += NB) {
@@ -533,7 +630,10 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
         if (kend < n) {
             TrsmArgs ta{A, lda, sA, ipiv, n, k0, nbo, A, lda, sA, kend, n, nullptr};
             const int ncol = n - kend;
-            hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3((ncol + 63) / 64, batch), dim3(64), 0, st, ta);
+            constexpr int CB = TrsmCols<T>::CB;
+            HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
+                             hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3((ncol + CB - 1) / CB, batch),
+                                                dim3(256), 0, st, ta));
             HARP_LAUNCH_CHECK();
             GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - kend, n - kend, nbo, kend, k0, k0, kend, kend, kend, T(-1),
                                         T(1), nullptr);
@@ -549,11 +649,12 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
                        int64_t ldx, int64_t sX, const int32_t* active, hipStream_t st) {
     constexpr int NB = LuCfg<T>::NB;
     harp_status s;
-    const dim3 tgrid((nrhs + 63) / 64, batch);
+    const dim3 tgrid((nrhs + TrsmCols<T>::CB - 1) / TrsmCols<T>::CB, batch);
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
         TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
-        hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), tgrid, dim3(64), 0, st, ta);
+        HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
+                         hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), tgrid, dim3(256), 0, st, ta));
         HARP_LAUNCH_CHECK();
         if (kend < n) {
             GemmArgs<T> g;
@@ -582,7 +683,8 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     for (int bk = nblk - 1; bk >= 0; --bk) {
         const int k0 = bk * NB, nbo = std::min(NB, n - k0);
         TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
-        hipLaunchKernelGGL((trsm_upper_kernel<T, NB>), tgrid, dim3(64), 0, st, ta);
+        HARP_PROF_LAUNCH(HARP_K_TRSM_U, st, 0.0, 0.0,
+                         hipLaunchKernelGGL((trsm_upper_kernel<T, NB>), tgrid, dim3(256), 0, st, ta));
         HARP_LAUNCH_CHECK();
         if (k0 > 0) {
             GemmArgs<T> g;
@@ -615,18 +717,23 @@ harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t
                     int batch, const int32_t* active, hipStream_t st) {
     const int64_t total = int64_t(rows) * cols;
     const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 2048));
-    hipLaunchKernelGGL((convert_kernel<Ti, To>), dim3(blocks, 1, batch), dim3(256), 0, st,
-                       static_cast<const Ti*>(src), lds, ss, static_cast<To*>(dst), ldd, sd, rows, cols, active);
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL((convert_kernel<Ti, To>), dim3(blocks, 1, batch), dim3(256), 0, st,
+                                        static_cast<const Ti*>(src), lds, ss, static_cast<To*>(dst), ldd, sd, rows,
+                                        cols, active));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
 
 harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, int batch, double* part, double* out,
                       hipStream_t st) {
-    hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 1, batch), dim3(256), 0, st,
-                       static_cast<const double2*>(M), ld, s, rows, cols, part);
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 1, batch), dim3(256), 0, st,
+                                        static_cast<const double2*>(M), ld, s, rows, cols, part));
     HARP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(sumsq_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, part, out, batch);
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL(sumsq_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, part, out,
+                                        batch));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
@@ -721,8 +828,10 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
                 return s;
             if (accumulate) {
                 const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
-                hipLaunchKernelGGL(axpy_kernel<float2>, dim3(blocks, 1, batch), dim3(256), 0, st,
-                                   static_cast<double2*>(d_X), ldx, stride_x, W.B32, n, mat, n, nrhs, active);
+                HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                                 hipLaunchKernelGGL(axpy_kernel<float2>, dim3(blocks, 1, batch), dim3(256), 0, st,
+                                                    static_cast<double2*>(d_X), ldx, stride_x, W.B32, n, mat, n,
+                                                    nrhs, active));
                 HARP_LAUNCH_CHECK();
                 return HARP_OK;
             }
@@ -766,7 +875,9 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
         g.alpha = -1.0;
         g.beta = 1.0;
         g.active = W.active;
-        if ((s = cgemm<double>(g, batch, st)) != HARP_OK) return s;
+        int n_act = 0;
+        for (int b = 0; b < batch; ++b) n_act += act[b];
+        if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
         if ((s = fro_norms(W.R, n, mat, n, nrhs, batch, W.part, W.norms + batch, st)) != HARP_OK) return s;
         if ((s = fro_norms(d_X, ldx, stride_x, n, nrhs, batch, W.part, W.norms + 2 * batch, st)) != HARP_OK) return s;
         HARP_HIP_CHECK(hipMemcpyAsync(hn.data(), W.norms, sizeof(double) * 3 * batch, hipMemcpyDeviceToHost, st));
@@ -794,8 +905,10 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
                                         reinterpret_cast<double*>(W.R), n, mat, W.active, st)) != HARP_OK)
                 return s;
             const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
-            hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st,
-                               static_cast<double2*>(d_X), ldx, stride_x, W.R, n, mat, n, nrhs, W.active);
+            HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                             hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st,
+                                                static_cast<double2*>(d_X), ldx, stride_x, W.R, n, mat, n, nrhs,
+                                                W.active));
             HARP_LAUNCH_CHECK();
         }
         for (int b = 0; b < batch; ++b) iters[b] += act[b];

@@ -5,6 +5,7 @@
 // B[:, j] = e_j (x) w, and the current at port i of solution column j is
 // Y_ij = sum_T w_T X[i N_m + T, j]  (Y = W^T X).
 #include "common.hpp"
+#include "prof.hpp"
 
 namespace harp {
 namespace {
@@ -69,9 +70,10 @@ extern "C" harp_status harp_port_rhs(const void* d_models, int64_t model_stride,
     if (ldb < n || (n_freq > 1 && stride_b < ldb * n_ant)) return HARP_E_ARG;
     const int64_t total = n * n_ant;
     const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
-    hipLaunchKernelGGL(port_rhs_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0, stream,
-                       static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
-                       static_cast<double2*>(d_B), ldb, stride_b);
+    HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
+                     hipLaunchKernelGGL(port_rhs_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0, stream,
+                                        static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                                        static_cast<double2*>(d_B), ldb, stride_b));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
@@ -87,10 +89,11 @@ extern "C" harp_status harp_port_admittance(const void* d_models, int64_t model_
     if (n_freq > 1 && (stride_x < ldx * n_ant || stride_y < ldy * n_ant)) return HARP_E_ARG;
     const int64_t total = int64_t(n_ant) * n_ant;
     const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
-    hipLaunchKernelGGL(port_admittance_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0, stream,
-                       static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
-                       static_cast<const double2*>(d_X), ldx, stride_x, static_cast<double2*>(d_Y), ldy,
-                       stride_y);
+    HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
+                     hipLaunchKernelGGL(port_admittance_kernel, dim3(blocks, unsigned(n_freq)), dim3(256), 0,
+                                        stream, static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                                        static_cast<const double2*>(d_X), ldx, stride_x, static_cast<double2*>(d_Y),
+                                        ldy, stride_y));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
