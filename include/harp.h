@@ -208,16 +208,22 @@ harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dty
 /* Embedded element patterns (Eqs. 5-6)                                      */
 /* ------------------------------------------------------------------------ */
 
-/* For each of n_ports coefficient columns of d_X (complex128, n x n_ports,
- * ld ldx) and each direction (theta, phi) (float64 radians, device):
+harp_status embedded_patterns_ws(int32_t n_mbf, int32_t n_ant, int32_t n_dir, size_t *bytes);
+
+/* Eqs. (5)-(6): for each of n_ports coefficient columns of d_X (complex128,
+ * n x n_ports, ld ldx; e.g. the solution for an excitation of each port) and
+ * each direction (theta, phi) (float64 radians, device):
  *   E = -(j omega mu0 / 4 pi) sum_T F_T(u) sum_i X[i N_m + T] e^{jk(u_x x_i + u_y y_i)}
  * projected on theta-hat and phi-hat, with F_T the radiation vector of MBF T
- * (sum over its samples of a s_perp e^{+jk u . rho}).  d_E: complex128
- * [n_ports][n_dir][2].  Asynchronous. */
+ * (sum over its samples of a s_hat e^{+jk u . rho}; the model blob carries the
+ * samples).  The far electric field is E e^{-jkr} / r.  d_E: complex128
+ * [n_ports][n_dir][2] (theta, phi).  Needs a workspace of
+ * embedded_patterns_ws(...) bytes.  Asynchronous. */
 harp_status embedded_patterns(const void *d_model, int32_t n_mbf, const double *d_x,
                               const double *d_y, int32_t n_ant, const void *d_X, int64_t ldx,
                               int32_t n_ports, const double *d_theta, const double *d_phi,
-                              int32_t n_dir, void *d_E, hipStream_t stream);
+                              int32_t n_dir, void *d_E, void *d_ws, size_t ws_bytes,
+                              hipStream_t stream);
 
 #ifdef __cplusplus
 }

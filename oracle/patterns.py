@@ -45,7 +45,7 @@ def embedded_patterns(freq, samples, x, y, X, theta, phi) -> np.ndarray:
     Fth, Fph = mbf_patterns(freq, samples, theta, phi)                  # (D, M)
     AF_phase = np.exp(1j * k * (np.outer(u[:, 0], x) + np.outer(u[:, 1], y)))  # (D, Na)
     Xr = np.asarray(X).reshape(na, n_mbf, -1)                           # (i, j, port)
-    AF = np.einsum("di,ijk->djk", AF_phase, Xr)                         # (D, M, port)
+    AF = np.einsum("di,ijk->djk", AF_phase, Xr, optimize=True)          # (D, M, port)
     pref = -1j * em.omega_mu(freq) / (4.0 * math.pi)
     Eth = pref * np.einsum("dj,djk->kd", Fth, AF)
     Eph = pref * np.einsum("dj,djk->kd", Fph, AF)

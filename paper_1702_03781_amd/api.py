@@ -327,10 +327,15 @@ def embedded_patterns(model: Model, x: torch.Tensor, y: torch.Tensor, X: torch.T
     n_dir = int(theta.numel())
     px, ldx, _ = _cm(X, "X")
     E = torch.empty((n_ports, n_dir, 2), dtype=torch.complex128, device=X.device)
-    check(lib().embedded_patterns(_ptr(model.blob), model.n_mbf, _ptr(x.contiguous()),
-                                  _ptr(y.contiguous()), n_ant, px, ldx, n_ports,
-                                  _ptr(theta.contiguous()), _ptr(phi.contiguous()), n_dir,
-                                  _ptr(E), _stream(X.device)), "embedded_patterns")
+    ws_b = ctypes.c_size_t()
+    check(lib().embedded_patterns_ws(model.n_mbf, n_ant, n_dir, ctypes.byref(ws_b)),
+          "embedded_patterns_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=X.device)
+    x, y = x.contiguous(), y.contiguous()
+    theta, phi = theta.contiguous(), phi.contiguous()
+    check(lib().embedded_patterns(_ptr(model.blob), model.n_mbf, _ptr(x), _ptr(y), n_ant, px, ldx,
+                                  n_ports, _ptr(theta), _ptr(phi), n_dir, _ptr(E), _ptr(ws),
+                                  ws_b.value, _stream(X.device)), "embedded_patterns")
     return E
 
 

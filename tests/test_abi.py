@@ -28,7 +28,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ["harp_fit", "harp_fill", "reduced_factor", "reduced_solve", "embedded_patterns",
               "harp_port_rhs", "harp_port_admittance", "harp_model_bytes", "harp_fit_ws",
-              "reduced_factor_ws", "reduced_solve_ws", "harp_status_str", "harp_version"]:
+              "reduced_factor_ws", "reduced_solve_ws", "embedded_patterns_ws", "harp_status_str",
+              "harp_version"]:
         assert n in names
 
 
