@@ -156,20 +156,25 @@ harp_status harp_port_admittance(const void *d_models, int64_t model_stride, int
 /* Dense reduced solve (Section I: Gaussian elimination, one RHS per port)   */
 /* ------------------------------------------------------------------------ */
 
+/* Bytes of the factor auxiliary buffer of reduced_factor / reduced_solve. */
 harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t *bytes);
 
 /* In-place LU factorisation with partial pivoting of `batch` n x n matrices
- * (complex64 or complex128, lda >= n): blocked right-looking elimination,
- * pivot = first row maximising |Re| + |Im| in the column.  On return the
- * upper triangle holds U and the strict lower triangle the multipliers of L;
- * d_ipiv[b * n + i] (int32, device) is the row exchanged with row i at step
- * i.  Row exchanges found in a later column block are not applied to the
- * multipliers of earlier blocks: the factors are meant for reduced_solve.
- * d_info[b] = 0, or i + 1 if U(i, i) is exactly zero (the factorisation then
- * continues; a solve with it is meaningless).  Asynchronous. */
+ * (complex64 or complex128, lda >= n, n <= 8192): blocked right-looking
+ * elimination, pivot = first row maximising |Re| + |Im| in the column.  On
+ * return the upper triangle holds U and the strict lower triangle the
+ * multipliers of L; d_ipiv[b * n + i] (int32, device) is the row exchanged with
+ * row i at step i.  The rows are grouped in solve groups of 256: the row
+ * exchanges of a group are applied to the multipliers of that group but not to
+ * those of earlier groups (the forward solve applies them group by group).
+ * d_aux (device, reduced_factor_ws bytes, caller-owned) receives the inverses
+ * of the diagonal 256 x 256 blocks of L and U and each group's row
+ * permutation; pass it unchanged to reduced_solve.  d_info[b] = 0, or i + 1 if
+ * U(i, i) is exactly zero (the factorisation then continues; a solve with it
+ * is meaningless).  Asynchronous. */
 harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void *d_A, int64_t lda,
-                           int64_t stride_a, int32_t *d_ipiv, int32_t *d_info, void *d_ws,
-                           size_t ws_bytes, hipStream_t stream);
+                           int64_t stride_a, int32_t *d_ipiv, int32_t *d_info, void *d_aux,
+                           size_t aux_bytes, hipStream_t stream);
 
 /* FP64 iterative refinement of a solve whose factors are complex64. */
 typedef struct {
@@ -189,8 +194,11 @@ typedef struct {
 harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
                              int32_t refine, size_t *bytes);
 
-/* Solve A X = B for `batch` systems with the factors of reduced_factor
- * (dtype as factored).  B and X are complex128 (n x nrhs).  With refine ==
+/* Solve A X = B for `batch` systems with the factors (d_LU, d_ipiv, d_aux) of
+ * reduced_factor (dtype as factored): per group of 256 rows, the group's row
+ * exchanges, the inverse unit-lower block and the update of the rows below;
+ * then per group backwards, the inverse upper block and the update of the rows
+ * above, all products on the matrix cores.  B and X are complex128 (n x nrhs).  With refine ==
  * NULL, X is the solve in the factor precision.  With refine != NULL: the
  * residual R = B - Z X is formed in FP64 against refine->d_Z, corrections
  * are solved with the factors and added in FP64, until the tolerance or
@@ -199,7 +207,7 @@ harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype 
  * system missed the tolerance. */
 harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
                           const void *d_LU, int64_t lda, int64_t stride_lu, const int32_t *d_ipiv,
-                          const void *d_B, int64_t ldb, int64_t stride_b, void *d_X, int64_t ldx,
+                          const void *d_aux, size_t aux_bytes, const void *d_B, int64_t ldb, int64_t stride_b, void *d_X, int64_t ldx,
                           int64_t stride_x, const harp_refine *refine,
                           harp_refine_report *report, void *d_ws, size_t ws_bytes,
                           hipStream_t stream);

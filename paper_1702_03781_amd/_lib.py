@@ -51,7 +51,7 @@ SIGNATURES = {
     "reduced_factor": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_sz,
                                c_vp]),
     "reduced_solve_ws": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_szp]),
-    "reduced_solve": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64,
+    "reduced_solve": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp, c_i64,
                               c_i64, c_vp, c_i64, c_i64, ctypes.POINTER(HarpRefine),
                               ctypes.POINTER(HarpRefineReport), c_vp, c_sz, c_vp]),
     "embedded_patterns_ws": (c_i32, [c_i32, c_i32, c_i32, c_szp]),

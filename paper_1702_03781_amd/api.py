@@ -254,9 +254,19 @@ def harp_port_admittance(models: ModelBatch, X: torch.Tensor, Y: torch.Tensor | 
 # factor, solve
 # --------------------------------------------------------------------------
 
-def reduced_factor(A: torch.Tensor):
-    """In-place LU with partial pivoting of a batch of column-major matrices.
-    Returns (ipiv, info) device tensors."""
+class Factors:
+    """LU factors of a batch (in place in `LU`), pivots, info, and the factor
+    auxiliary buffer (inverse diagonal blocks, group permutations)."""
+
+    def __init__(self, LU, ipiv, info, aux):
+        self.LU, self.ipiv, self.info, self.aux = LU, ipiv, info, aux
+
+    def __iter__(self):            # (ipiv, info) unpacking for convenience
+        return iter((self.ipiv, self.info))
+
+
+def reduced_factor(A: torch.Tensor) -> Factors:
+    """In-place LU with partial pivoting of a batch of column-major matrices."""
     if A.dim() == 2:
         A = A.unsqueeze(0)
     dt = _DT[A.dtype]
@@ -266,19 +276,18 @@ def reduced_factor(A: torch.Tensor):
     info = torch.empty(b, dtype=torch.int32, device=A.device)
     ws_b = ctypes.c_size_t()
     check(lib().reduced_factor_ws(n, b, dt, ctypes.byref(ws_b)), "reduced_factor_ws")
-    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=A.device)
-    check(lib().reduced_factor(n, b, dt, pa, lda, sa, _ptr(ipiv), _ptr(info), _ptr(ws),
+    aux = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=A.device)
+    check(lib().reduced_factor(n, b, dt, pa, lda, sa, _ptr(ipiv), _ptr(info), _ptr(aux),
                                ws_b.value, _stream(A.device)), "reduced_factor")
-    return ipiv, info
+    return Factors(A, ipiv, info, aux)
 
 
-def reduced_solve(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor,
-                  X: torch.Tensor | None = None, Z64: torch.Tensor | None = None,
-                  tol: float = 1e-12, max_iter: int = 10, raise_noconv: bool = True):
+def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
+                  Z64: torch.Tensor | None = None, tol: float = 1e-12, max_iter: int = 10,
+                  raise_noconv: bool = True):
     """Solve with the factors of reduced_factor; optional FP64 refinement
     against Z64.  Returns (X, reports or None)."""
-    if LU.dim() == 2:
-        LU = LU.unsqueeze(0)
+    LU = F.LU
     if B.dim() == 2:
         B = B.unsqueeze(0)
     dt = _DT[LU.dtype]
@@ -299,7 +308,8 @@ def reduced_solve(LU: torch.Tensor, ipiv: torch.Tensor, B: torch.Tensor,
     check(lib().reduced_solve_ws(n, nrhs, b, dt, int(ref is not None), ctypes.byref(ws_b)),
           "reduced_solve_ws")
     ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=LU.device)
-    st = lib().reduced_solve(n, nrhs, b, dt, pl, lda, sl, _ptr(ipiv), pb, ldb, sb, px, ldx, sx,
+    st = lib().reduced_solve(n, nrhs, b, dt, pl, lda, sl, _ptr(F.ipiv), _ptr(F.aux),
+                             F.aux.numel(), pb, ldb, sb, px, ldx, sx,
                              ctypes.byref(ref) if ref is not None else None,
                              rep if rep is not None else None, _ptr(ws), ws_b.value,
                              _stream(LU.device))
@@ -349,7 +359,7 @@ def default_grid(P: int, Q: int):
 
 __all__ = [
     "Model", "ModelBatch", "harp_fit", "pack_model", "stack_models", "harp_fill",
-    "harp_port_rhs", "harp_port_admittance", "reduced_factor", "reduced_solve",
+    "harp_port_rhs", "harp_port_admittance", "reduced_factor", "reduced_solve", "Factors",
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid",
 ]
@@ -387,6 +397,10 @@ class StationSolver:
         self.finfo = torch.empty(nf, dtype=torch.int32, device=dev)
         self.ipiv = torch.empty((nf, n), dtype=torch.int32, device=dev)
         dt = C64 if mode == "refined" else C128
+        aux_b = ctypes.c_size_t()
+        check(lib().reduced_factor_ws(n, nf, dt, ctypes.byref(aux_b)), "reduced_factor_ws")
+        self.aux = torch.empty(max(1, aux_b.value), dtype=torch.uint8, device=dev)
+        self.aux_bytes = aux_b.value
         ws_b = ctypes.c_size_t()
         check(lib().reduced_solve_ws(n, self.n_ant, nf, dt, int(mode == "refined"),
                                      ctypes.byref(ws_b)), "reduced_solve_ws")
@@ -409,12 +423,13 @@ class StationSolver:
               "harp_port_rhs")
         pf, ldf, sf = (p32, ld32, s32) if refined else (pz, ldz, sz)
         dt = C64 if refined else C128
-        check(L.reduced_factor(n, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.finfo), None, 0,
-                               st), "reduced_factor")
+        check(L.reduced_factor(n, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.finfo),
+                               _ptr(self.aux), self.aux_bytes, st), "reduced_factor")
         px, ldx, sx = _cm(self.X, "X")
         ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter)) if refined else None
         rep = (HarpRefineReport * nf)() if refined else None
-        check(L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), pb, ldb, sb, px, ldx,
+        check(L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.aux),
+                              self.aux_bytes, pb, ldb, sb, px, ldx,
                               sx, ctypes.byref(ref) if ref is not None else None, rep,
                               _ptr(self.ws), self.ws_bytes, st), "reduced_solve")
         py, ldy, sy = _cm(self.Y, "Y")

@@ -64,7 +64,11 @@ template <typename T> struct GemmArgs {
     T* D;
     int64_t ldd, sD;
     T alpha, beta;
-    const int32_t* active;       // optional [batch]: 0 skips that matrix
+    const int32_t* active;       // optional [outer batch]: 0 skips that matrix
+    // optional second batch level: grid z = outer * inner + i, operand X at
+    // X + outer * sX + i * sX2 (e.g. several blocks of one matrix)
+    int inner = 1;
+    int64_t sA2 = 0, sB2 = 0, sC2 = 0, sD2 = 0;
 };
 
 template <typename T, int BM, int BN, int BK>
@@ -78,14 +82,14 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
     static_assert(BM % 16 == 0 && BN % 32 == 0 && BK % 2 == 0, "tile shape");
     static_assert(A_PER_T >= 1 && B_PER_T >= 1, "tile too small for 256 threads");
 
-    const int bz = blockIdx.z;
+    const int bz = blockIdx.z / g.inner, bi = blockIdx.z % g.inner;
     if (g.active && g.active[bz] == 0) return;
     const int tiles_m = (g.M + BM - 1) / BM;
     const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
     const int row0 = tm * BM, col0 = tn * BN;
 
-    const ct* A = reinterpret_cast<const ct*>(g.A) + size_t(bz) * g.sA;
-    const ct* B = reinterpret_cast<const ct*>(g.B) + size_t(bz) * g.sB;
+    const ct* A = reinterpret_cast<const ct*>(g.A) + size_t(bz) * g.sA + size_t(bi) * g.sA2;
+    const ct* B = reinterpret_cast<const ct*>(g.B) + size_t(bz) * g.sB + size_t(bi) * g.sB2;
 
     __shared__ ct As[2][BK][BM];
     __shared__ ct Bs[2][BN][BK + 1];
@@ -131,7 +135,7 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
     const int M2 = 2 * g.M;
     acc_t acc[RB][CB];
     {
-        const T* Cr = g.C ? g.C + 2 * size_t(bz) * g.sC : nullptr;
+        const T* Cr = g.C ? g.C + 2 * (size_t(bz) * g.sC + size_t(bi) * g.sC2) : nullptr;
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
 
     // epilogue in the real view of the interleaved storage: real row 2i + part
     // is exactly the MFMA output row
-    T* Dr = g.D + 2 * size_t(bz) * g.sD;
+    T* Dr = g.D + 2 * (size_t(bz) * g.sD + size_t(bi) * g.sD2);
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
 #pragma unroll
@@ -213,20 +217,22 @@ template <> struct GemmTile<double> {
     static constexpr int BM = 32, BN = 64, BK = 16;
 };
 
-// Enqueue D = beta C + alpha A B for `batch` matrices.  M, N, K may be zero.
-// eff_batch (< 0: batch) is the number of matrices not skipped by g.active,
-// used only for the work accounting of the profiler.
+// Enqueue D = beta C + alpha A B for `batch` (x g.inner) matrices.  M, N, K
+// may be zero.  eff_batch (< 0: batch) is the number of outer matrices not
+// skipped by g.active, used only for the work accounting of the profiler.
 template <typename T>
 inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
-    if (g.M <= 0 || g.N <= 0 || batch <= 0) return HARP_OK;
+    if (g.M <= 0 || g.N <= 0 || batch <= 0 || g.inner <= 0) return HARP_OK;
+    if (int64_t(batch) * g.inner > 65535) return HARP_E_ARG;
     constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN, BK = GemmTile<T>::BK;
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     // K == 0 runs the same kernel with an empty contraction: D = beta C
-    const double nb = double(eff_batch < 0 ? batch : eff_batch);
+    const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
     HARP_PROF_LAUNCH(sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64, stream,
                      8.0 * double(g.M) * double(g.N) * double(g.K) * nb, 0.0,
-                     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK>), dim3(unsigned(tiles), 1u, unsigned(batch)),
-                                        dim3(256), 0, stream, g));
+                     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK>),
+                                        dim3(unsigned(tiles), 1u, unsigned(batch * g.inner)), dim3(256), 0, stream,
+                                        g));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }

@@ -297,8 +297,9 @@ struct TrsmArgs {
     int n, k0, nbo;
     void* X;
     int64_t ldx, sX;
-    int c_begin, c_end;    // columns of X to process
+    int c_begin, c_end;    // columns of X to exchange and solve
     const int32_t* active;
+    int l_begin = 0, l_end = 0;  // columns of X that only take the row exchanges
 };
 
 // Block-row solves on CB columns per 256-thread workgroup.  The block row
@@ -323,14 +324,19 @@ __global__ void __launch_bounds__(256) laswp_trsm_lower_kernel(TrsmArgs ta) {
     V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
     const int32_t* ipiv = ta.ipiv + size_t(b) * ta.n;
     const int k0 = ta.k0, nbo = ta.nbo, tid = threadIdx.x;
-    const int c0 = ta.c_begin + blockIdx.x * CB;
-    const int ncols = min(CB, ta.c_end - c0);
+    // the first tiles take the exchange-only columns [l_begin, l_end)
+    const int left_tiles = (ta.l_end - ta.l_begin + CB - 1) / CB;
+    const bool left = int(blockIdx.x) < left_tiles;
+    const int c0 = left ? ta.l_begin + blockIdx.x * CB : ta.c_begin + (blockIdx.x - left_tiles) * CB;
+    const int ncols = min(CB, (left ? ta.l_end : ta.c_end) - c0);
     __shared__ V Ls[NB][NB + 1];
     __shared__ V S[CB][2 * NB + 1];
     __shared__ int pv[NB], cand[2 * NB], src[2 * NB];
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e % NB, j = e / NB;
-        Ls[i][j] = (i < nbo && j < nbo && i > j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+    if (!left) {
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e % NB, j = e / NB;
+            Ls[i][j] = (i < nbo && j < nbo && i > j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
+        }
     }
     for (int e = tid; e < nbo; e += 256) pv[e] = ipiv[k0 + e];
     __syncthreads();
@@ -351,6 +357,15 @@ __global__ void __launch_bounds__(256) laswp_trsm_lower_kernel(TrsmArgs ta) {
         S[c][t] = X[size_t(c0 + c) * ta.ldx + src[t]];
     }
     __syncthreads();
+    if (left) {
+        for (int e = tid; e < n2 * ncols; e += 256) {
+            const int t = e % n2, c = e / n2;
+            const int r = cand[t];
+            if (t >= nbo && r < k0 + nbo) continue;   // written by its top-row entry
+            X[size_t(c0 + c) * ta.ldx + r] = S[c][t];
+        }
+        return;
+    }
     // rows displaced below the block row
     for (int e = tid; e < nbo * ncols; e += 256) {
         const int t = nbo + e % nbo, c = e / nbo;
@@ -453,6 +468,141 @@ __global__ void __launch_bounds__(256) trsm_upper_kernel(TrsmArgs ta) {
 }
 
 // ---------------------------------------------------------------------------
+// inverses of the diagonal blocks (solve groups of SB rows)
+//
+// After the factorisation the unit-lower and upper SB x SB diagonal blocks of
+// every group are copied (identity beyond n) and inverted in place by
+// recursive doubling: 16 x 16 blocks by substitution, then for s = 32..SB
+//   L: [[A, 0], [C, D]]^-1 = [[A^-1, 0], [-D^-1 C A^-1, D^-1]]
+//   U: [[A, B], [0, D]]^-1 = [[A^-1, -A^-1 B D^-1], [0, D^-1]]
+// with the two products on the matrix cores.  The solves then apply each
+// group with matrix-core products instead of substitution.
+// ---------------------------------------------------------------------------
+
+constexpr int kSB = 256;         // rows of a solve group
+constexpr int kInv0 = 16;        // base block inverted by substitution
+
+// per (matrix, group) record: [Linv SBxSB | Uinv SBxSB | temp SB*SB/4]
+constexpr int64_t kRec = 2 * int64_t(kSB) * kSB + int64_t(kSB) * kSB / 4;
+
+template <typename T>
+__global__ void __launch_bounds__(256) extract_diag_kernel(const T* __restrict__ LUr, int64_t lda, int64_t sA,
+                                                           int n, int G, T* __restrict__ aux) {
+    using V = typename C2<T>::t;
+    const int g = blockIdx.x, b = blockIdx.y;
+    const V* LU = reinterpret_cast<const V*>(LUr) + size_t(b) * sA;
+    V* rec = reinterpret_cast<V*>(aux) + (size_t(b) * G + g) * kRec;
+    V* Lb = rec;
+    V* Ub = rec + int64_t(kSB) * kSB;
+    for (int e = threadIdx.x; e < kSB * kSB; e += 256) {
+        const int i = e % kSB, j = e / kSB;
+        const int gi = g * kSB + i, gj = g * kSB + j;
+        const bool in = gi < n && gj < n;
+        const V v = in ? LU[size_t(gj) * lda + gi] : V{T(0), T(0)};
+        const V one{T(1), T(0)}, zero{T(0), T(0)};
+        Lb[e] = (i == j) ? one : ((i > j && in) ? v : zero);
+        Ub[e] = (i <= j && in) ? v : ((i == j) ? one : zero);
+    }
+}
+
+// one workgroup inverts one 16 x 16 diagonal block of Linv (z = 0) or Uinv (z = 1)
+template <typename T>
+__global__ void __launch_bounds__(64) tri_inv16_kernel(T* __restrict__ aux, int G) {
+    using V = typename C2<T>::t;
+    const int blk = blockIdx.x % (kSB / kInv0), rg = blockIdx.x / (kSB / kInv0);   // rg = b * G + g
+    const bool upper = blockIdx.z == 1;
+    V* M = reinterpret_cast<V*>(aux) + size_t(rg) * kRec + (upper ? int64_t(kSB) * kSB : 0);
+    V* D = M + size_t(blk) * kInv0 * (kSB + 1);   // top-left of the 16 x 16 block, ld kSB
+    __shared__ V a[kInv0][kInv0 + 1];
+    const int t = threadIdx.x;
+    for (int e = t; e < kInv0 * kInv0; e += 64) a[e % kInv0][e / kInv0] = D[size_t(e / kInv0) * kSB + e % kInv0];
+    __syncthreads();
+    if (t >= kInv0) return;
+    const int j = t;   // this thread's column of the inverse
+    V x[kInv0];
+#pragma unroll
+    for (int i = 0; i < kInv0; ++i) x[i] = V{T(0), T(0)};
+    if (!upper) {
+        x[j] = V{T(1), T(0)};
+#pragma unroll
+        for (int i = 1; i < kInv0; ++i) {
+            V acc = x[i];
+#pragma unroll
+            for (int q = 0; q < i; ++q) acc = cfms(acc, a[i][q], x[q]);
+            x[i] = i > j ? acc : x[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = kInv0 - 1; i >= 0; --i) {
+            V acc = (i == j) ? V{T(1), T(0)} : V{T(0), T(0)};
+#pragma unroll
+            for (int q = i + 1; q < kInv0; ++q) acc = cfms(acc, a[i][q], x[q]);
+            x[i] = i <= j ? cm(acc, crecip(a[i][i])) : V{T(0), T(0)};
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kInv0; ++i) D[size_t(j) * kSB + i] = x[i];
+}
+
+// composite row permutation of each solve group: cand[t] = row t of the
+// group (t < sb) or its t-sb-th pivot row; src[t] = the row whose content ends
+// at cand[t] after the group's exchanges (walking them backwards)
+__global__ void __launch_bounds__(256) group_perm_kernel(const int32_t* __restrict__ ipiv, int n, int G,
+                                                         int32_t* __restrict__ perm) {
+    const int g = blockIdx.x, b = blockIdx.y;
+    const int g0 = g * kSB, sb = min(kSB, n - g0);
+    const int32_t* pv = ipiv + size_t(b) * n + g0;
+    int32_t* cand = perm + (size_t(b) * G + g) * 4 * kSB;
+    int32_t* src = cand + 2 * kSB;
+    for (int e = threadIdx.x; e < 2 * sb; e += 256) {
+        const int r = e < sb ? g0 + e : pv[e - sb];
+        int sr = r;
+        for (int q = sb - 1; q >= 0; --q) {
+            if (sr == g0 + q) sr = pv[q];
+            else if (sr == pv[q]) sr = g0 + q;
+        }
+        cand[e] = r;
+        src[e] = sr;
+    }
+}
+
+// rows [g0, g0 + sb) of X after the group's row exchanges go to Tm (ld SB);
+// rows the exchanges push below the group are written back into X
+template <typename T>
+__global__ void __launch_bounds__(256) group_gather_kernel(const int32_t* __restrict__ perm, int G, int g, int sb,
+                                                           T* __restrict__ Xr, int64_t ldx, int64_t sX, int nrhs,
+                                                           T* __restrict__ Tr, int64_t sT,
+                                                           const int32_t* __restrict__ active) {
+    using V = typename C2<T>::t;
+    constexpr int CG = 16;
+    const int b = blockIdx.y;
+    if (active && active[b] == 0) return;
+    V* X = reinterpret_cast<V*>(Xr) + size_t(b) * sX;
+    V* Tm = reinterpret_cast<V*>(Tr) + size_t(b) * sT;
+    const int32_t* cand = perm + (size_t(b) * G + g) * 4 * kSB;
+    const int32_t* src = cand + 2 * kSB;
+    const int g0 = g * kSB;
+    const int c0 = blockIdx.x * CG, ncols = min(CG, nrhs - c0);
+    const int tid = threadIdx.x;
+    __shared__ V S[CG][2 * kSB + 1];
+    const int n2 = 2 * sb;
+    for (int e = tid; e < n2 * ncols; e += 256) {
+        const int t = e % n2, c = e / n2;
+        S[c][t] = X[size_t(c0 + c) * ldx + src[t]];
+    }
+    __syncthreads();
+    for (int e = tid; e < n2 * ncols; e += 256) {
+        const int t = e % n2, c = e / n2;
+        if (t < sb) {
+            Tm[size_t(c0 + c) * kSB + t] = S[c][t];
+        } else {
+            const int r = cand[t];
+            if (r >= g0 + sb) X[size_t(c0 + c) * ldx + r] = S[c][t];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // small helpers: zero info, conversions, Frobenius norms, axpy
 // ---------------------------------------------------------------------------
 
@@ -536,37 +686,39 @@ template <typename T> struct LuCfg {
 };
 
 // Panel width: the register-resident panel holds RPT x W complex values per
-// thread (8 rows per thread); W shrinks as the matrix grows so the panel stays
-// in registers at the thread count the height needs.
+// thread with 1024 threads (64 VGPRs of budget per lane for the panel); W
+// shrinks as the matrix grows so the panel stays in registers.
 template <typename T> inline int panel_width(int n) {
     if (sizeof(T) == 4) return n <= 4096 ? 8 : 4;
     return n <= 2048 ? 8 : (n <= 4096 ? 4 : 2);
 }
 
-// true when a panel of 8 rows x W complex values per thread fits the VGPR
+// true when a panel of RPT rows x W complex values per thread fits the VGPR
 // budget of an NT-thread workgroup (512 / (NT / 256) per lane, minus headroom)
-template <typename T, int NT, int W> constexpr bool panel_fits() {
-    return 8 * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
+template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
+    return RPT * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
 }
 
-template <typename T, int NT, int W>
-harp_status launch_getf2_nt(const PanelArgs& pa, int batch, hipStream_t st) {
-    if constexpr (panel_fits<T, NT, W>()) {
+template <typename T, int NT, int RPT, int W>
+harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
+    if constexpr (panel_fits_r<T, NT, RPT, W>()) {
         HARP_PROF_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0,
-                         hipLaunchKernelGGL((getf2_kernel<T, NT, 8, W>), dim3(batch), dim3(NT), 0, st, pa));
+                         hipLaunchKernelGGL((getf2_kernel<T, NT, RPT, W>), dim3(batch), dim3(NT), 0, st, pa));
         HARP_LAUNCH_CHECK();
         return HARP_OK;
     }
     return HARP_E_ARG;
 }
 
+// 1024 threads (16 waves) hide the per-column latency best; rows per thread
+// grow with the panel height
 template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
     if (pa.w > W) return HARP_E_ARG;
-    if (m <= 256 * 8) return launch_getf2_nt<T, 256, W>(pa, batch, st);
-    if (m <= 512 * 8) return launch_getf2_nt<T, 512, W>(pa, batch, st);
-    if (m <= 1024 * 8) return launch_getf2_nt<T, 1024, W>(pa, batch, st);
+    if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, W>(pa, batch, st);
+    if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, W>(pa, batch, st);
+    if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, W>(pa, batch, st);
     return HARP_E_ARG;
 }
 
@@ -627,14 +779,22 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                 if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
             }
         }
-        if (kend < n) {
+        // row exchanges reach the block row to the right (then the unit-lower
+        // solve and the trailing update) and the earlier columns of the same
+        // solve group (so each group's multipliers share one row order)
+        const int lbeg = (k0 / kSB) * kSB;
+        if (kend < n || lbeg < k0) {
             TrsmArgs ta{A, lda, sA, ipiv, n, k0, nbo, A, lda, sA, kend, n, nullptr};
-            const int ncol = n - kend;
+            ta.l_begin = lbeg;
+            ta.l_end = k0;
             constexpr int CB = TrsmCols<T>::CB;
+            const int tiles = (n - kend + CB - 1) / CB + (k0 - lbeg + CB - 1) / CB;
             HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
-                             hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3((ncol + CB - 1) / CB, batch),
-                                                dim3(256), 0, st, ta));
+                             hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3(tiles, batch), dim3(256), 0,
+                                                st, ta));
             HARP_LAUNCH_CHECK();
+        }
+        if (kend < n) {
             GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - kend, n - kend, nbo, kend, k0, k0, kend, kend, kend, T(-1),
                                         T(1), nullptr);
             if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
@@ -643,71 +803,151 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
     return HARP_OK;
 }
 
-// in-place solve of X (n x nrhs, same precision as the factors)
+// Inverses of the diagonal blocks of every solve group and the groups'
+// composite permutations, written into the factor auxiliary buffer.
+inline int n_groups(int n) { return (n + kSB - 1) / kSB; }
+inline size_t aux_bytes(int n, int batch, int csize) {
+    const int64_t G = n_groups(n);
+    return size_t(align256(int64_t(batch) * G * kRec * csize) + align256(int64_t(batch) * G * 4 * kSB * 4));
+}
+template <typename T> inline int32_t* aux_perm(T* aux, int n, int batch) {
+    const int64_t G = n_groups(n);
+    return reinterpret_cast<int32_t*>(reinterpret_cast<char*>(aux) +
+                                      align256(int64_t(batch) * G * kRec * 2 * int64_t(sizeof(T))));
+}
+
 template <typename T>
-harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int64_t sL, const int32_t* ipiv, T* X,
-                       int64_t ldx, int64_t sX, const int32_t* active, hipStream_t st) {
-    constexpr int NB = LuCfg<T>::NB;
+harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, const int32_t* ipiv, T* aux,
+                        hipStream_t st) {
+    const int G = n_groups(n);
     harp_status s;
-    const dim3 tgrid((nrhs + TrsmCols<T>::CB - 1) / TrsmCols<T>::CB, batch);
-    for (int k0 = 0; k0 < n; k0 += NB) {
-        const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
-        TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
-        HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
-                         hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), tgrid, dim3(256), 0, st, ta));
-        HARP_LAUNCH_CHECK();
-        if (kend < n) {
-            GemmArgs<T> g;
-            g.M = n - kend;
-            g.N = nrhs;
-            g.K = nbo;
-            g.A = LU + 2 * (size_t(k0) * lda + kend);
-            g.lda = lda;
-            g.sA = sL;
-            g.B = X + 2 * size_t(k0);
-            g.ldb = ldx;
-            g.sB = sX;
-            g.C = X + 2 * size_t(kend);
-            g.ldc = ldx;
-            g.sC = sX;
-            g.D = X + 2 * size_t(kend);
-            g.ldd = ldx;
-            g.sD = sX;
-            g.alpha = T(-1);
-            g.beta = T(1);
-            g.active = active;
-            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL(group_perm_kernel, dim3(G, batch), dim3(256), 0, st, ipiv, n, G,
+                                        aux_perm(aux, n, batch)));
+    HARP_LAUNCH_CHECK();
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL((extract_diag_kernel<T>), dim3(G, batch), dim3(256), 0, st, LU, lda, sA, n,
+                                        G, aux));
+    HARP_LAUNCH_CHECK();
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL((tri_inv16_kernel<T>), dim3(G * batch * (kSB / kInv0), 1, 2), dim3(64), 0,
+                                        st, aux, G));
+    HARP_LAUNCH_CHECK();
+    const int64_t blk = int64_t(kSB) * kSB;
+    for (int sz = 2 * kInv0; sz <= kSB; sz *= 2) {
+        const int h = sz / 2;
+        for (int upper = 0; upper < 2; ++upper) {
+            T* M = aux + 2 * (upper ? blk : 0);          // first record's L or U block
+            T* tmp = aux + 2 * (2 * blk);                // first record's temp
+            // block i of size sz starts at i sz (SB + 1); its quadrants:
+            const int64_t q11 = 0, q21 = h, q12 = int64_t(h) * kSB, q22 = int64_t(h) * (kSB + 1);
+            GemmArgs<T> g1{}, g2{};
+            for (GemmArgs<T>* g : {&g1, &g2}) {
+                g->M = h;
+                g->N = h;
+                g->K = h;
+                g->beta = T(0);
+                g->C = nullptr;
+                g->active = nullptr;
+                g->inner = kSB / sz;
+            }
+            // L: tmp = C A^-1, C = -D^-1 tmp ;  U: tmp = B D^-1, B = -A^-1 tmp
+            g1.A = M + 2 * (upper ? q12 : q21);
+            g1.B = M + 2 * (upper ? q22 : q11);
+            g1.D = tmp;
+            g2.A = M + 2 * (upper ? q11 : q22);
+            g2.B = tmp;
+            g2.D = M + 2 * (upper ? q12 : q21);
+            g1.lda = g1.ldb = kSB;
+            g1.ldd = h;
+            g1.ldc = h;
+            g2.lda = kSB;
+            g2.ldb = h;
+            g2.ldd = kSB;
+            g2.ldc = kSB;
+            g1.alpha = T(1);
+            g2.alpha = T(-1);
+            g1.sA = g1.sB = g1.sD = kRec;
+            g2.sA = g2.sB = g2.sD = kRec;
+            g1.sA2 = g1.sB2 = int64_t(sz) * (kSB + 1);
+            g1.sD2 = int64_t(h) * h;
+            g2.sA2 = g2.sD2 = int64_t(sz) * (kSB + 1);
+            g2.sB2 = int64_t(h) * h;
+            if ((s = cgemm<T>(g1, batch * G, st)) != HARP_OK) return s;
+            if ((s = cgemm<T>(g2, batch * G, st)) != HARP_OK) return s;
         }
     }
-    const int nblk = (n + NB - 1) / NB;
-    for (int bk = nblk - 1; bk >= 0; --bk) {
-        const int k0 = bk * NB, nbo = std::min(NB, n - k0);
-        TrsmArgs ta{LU, lda, sL, ipiv, n, k0, nbo, X, ldx, sX, 0, nrhs, active};
-        HARP_PROF_LAUNCH(HARP_K_TRSM_U, st, 0.0, 0.0,
-                         hipLaunchKernelGGL((trsm_upper_kernel<T, NB>), tgrid, dim3(256), 0, st, ta));
+    return HARP_OK;
+}
+
+// in-place solve of X (n x nrhs, same precision as the factors) by groups of
+// SB rows: forward: gather the group's rows through its exchanges, apply the
+// inverse unit-lower block, update the rows below; backward: apply the inverse
+// upper block, update the rows above.  Tm: SB x nrhs per matrix.
+template <typename T>
+harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int64_t sL, const T* aux, T* X,
+                       int64_t ldx, int64_t sX, T* Tm, const int32_t* active, hipStream_t st) {
+    const int G = n_groups(n);
+    const int64_t sT = int64_t(kSB) * nrhs;
+    const int32_t* perm = aux_perm(const_cast<T*>(aux), n, batch);
+    const int64_t blk = int64_t(kSB) * kSB;
+    harp_status s;
+    auto gemm = [&](int M, int N, int K, const T* A, int64_t lda_, int64_t sA_, const T* B, int64_t ldb_,
+                    int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta) {
+        GemmArgs<T> g{};
+        g.M = M;
+        g.N = N;
+        g.K = K;
+        g.A = A;
+        g.lda = lda_;
+        g.sA = sA_;
+        g.B = B;
+        g.ldb = ldb_;
+        g.sB = sB_;
+        g.C = beta != T(0) ? D : nullptr;
+        g.ldc = ldd_;
+        g.sC = sD_;
+        g.D = D;
+        g.ldd = ldd_;
+        g.sD = sD_;
+        g.alpha = alpha;
+        g.beta = beta;
+        g.active = active;
+        return cgemm<T>(g, batch, st);
+    };
+    for (int gi = 0; gi < G; ++gi) {
+        const int g0 = gi * kSB, sb = std::min(kSB, n - g0), gend = g0 + sb;
+        HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
+                         hipLaunchKernelGGL((group_gather_kernel<T>), dim3((nrhs + 15) / 16, batch), dim3(256), 0,
+                                            st, perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
         HARP_LAUNCH_CHECK();
-        if (k0 > 0) {
-            GemmArgs<T> g;
-            g.M = k0;
-            g.N = nrhs;
-            g.K = nbo;
-            g.A = LU + 2 * (size_t(k0) * lda);
-            g.lda = lda;
-            g.sA = sL;
-            g.B = X + 2 * size_t(k0);
-            g.ldb = ldx;
-            g.sB = sX;
-            g.C = X;
-            g.ldc = ldx;
-            g.sC = sX;
-            g.D = X;
-            g.ldd = ldx;
-            g.sD = sX;
-            g.alpha = T(-1);
-            g.beta = T(1);
-            g.active = active;
-            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
-        }
+        const T* Linv = aux + 2 * (int64_t(gi) * kRec);
+        if ((s = gemm(sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX, T(1), T(0))) !=
+            HARP_OK)
+            return s;
+        if (gend < n &&
+            (s = gemm(n - gend, nrhs, sb, LU + 2 * (size_t(g0) * lda + gend), lda, sL, X + 2 * size_t(g0), ldx, sX,
+                      X + 2 * size_t(gend), ldx, sX, T(-1), T(1))) != HARP_OK)
+            return s;
+    }
+    for (int gi = G - 1; gi >= 0; --gi) {
+        const int g0 = gi * kSB, sb = std::min(kSB, n - g0);
+        const T* Uinv = aux + 2 * (int64_t(gi) * kRec + blk);
+        if ((s = gemm(sb, nrhs, sb, Uinv, kSB, G * kRec, X + 2 * size_t(g0), ldx, sX, Tm, kSB, sT, T(1), T(0))) !=
+            HARP_OK)
+            return s;
+        if (g0 > 0 && (s = gemm(g0, nrhs, sb, LU + 2 * (size_t(g0) * lda), lda, sL, Tm, kSB, sT, X, ldx, sX, T(-1),
+                                T(1))) != HARP_OK)
+            return s;
+        // copy the group's solution back
+        using V = typename C2<T>::t;
+        const int64_t total = int64_t(sb) * nrhs;
+        const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 1024));
+        HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                         hipLaunchKernelGGL((convert_kernel<V, V>), dim3(blocks, 1, batch), dim3(256), 0, st,
+                                            reinterpret_cast<const V*>(Tm), int64_t(kSB), sT,
+                                            reinterpret_cast<V*>(X) + g0, ldx, sX, sb, nrhs, active));
+        HARP_LAUNCH_CHECK();
     }
     return HARP_OK;
 }
@@ -741,6 +981,7 @@ harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, 
 struct SolveWs {
     float2* B32;      // n x nrhs complex64 per matrix (ld n)
     double2* R;       // n x nrhs complex128 per matrix (ld n)
+    void* Tm;         // SB x nrhs per matrix in the factor precision (group temp)
     double* part;     // [batch][kNormBlocks]
     double* norms;    // [3][batch]: ||Z||, ||R||, ||X||
     int32_t* active;  // [batch]
@@ -758,6 +999,7 @@ size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveW
     SolveWs& W = w ? *w : tmp;
     W.B32 = reinterpret_cast<float2*>(take((dtype == HARP_C64) ? mat * batch * 8 : 0));
     W.R = reinterpret_cast<double2*>(take(refine ? mat * batch * 16 : 0));
+    W.Tm = take(int64_t(kSB) * nrhs * batch * (dtype == HARP_C64 ? 8 : 16));
     W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * kNormBlocks * 8 : 0));
     W.norms = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 3 * 8 : 0));
     W.active = reinterpret_cast<int32_t*>(take(refine ? int64_t(batch) * 4 : 0));
@@ -771,23 +1013,28 @@ using namespace harp;
 
 extern "C" harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t* bytes) {
     if (!bytes || n <= 0 || batch <= 0 || (dtype != HARP_C64 && dtype != HARP_C128)) return HARP_E_ARG;
-    *bytes = 0;
+    *bytes = aux_bytes(n, batch, dtype == HARP_C64 ? 8 : 16);
     return HARP_OK;
 }
 
 extern "C" harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void* d_A, int64_t lda,
-                                      int64_t stride_a, int32_t* d_ipiv, int32_t* d_info, void* d_ws, size_t ws_bytes,
-                                      hipStream_t stream) {
-    (void)d_ws;
-    (void)ws_bytes;
-    if (!d_A || !d_ipiv || !d_info || n <= 0 || batch <= 0 || batch > 65535) return HARP_E_ARG;
+                                      int64_t stride_a, int32_t* d_ipiv, int32_t* d_info, void* d_aux,
+                                      size_t aux_size, hipStream_t stream) {
+    if (!d_A || !d_ipiv || !d_info || n <= 0 || batch <= 0) return HARP_E_ARG;
     if (n > 8192) return HARP_E_ARG;
     if (lda < n || (batch > 1 && stride_a < lda * n)) return HARP_E_ARG;
-    if (dtype == HARP_C64)
-        return factor_impl<float>(n, batch, static_cast<float*>(d_A), lda, stride_a, d_ipiv, d_info, stream);
-    if (dtype == HARP_C128)
-        return factor_impl<double>(n, batch, static_cast<double*>(d_A), lda, stride_a, d_ipiv, d_info, stream);
-    return HARP_E_ARG;
+    if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
+    if (int64_t(batch) * n_groups(n) * (kSB / kInv0) > 65535 || batch > 65535) return HARP_E_ARG;
+    if (!d_aux || aux_size < aux_bytes(n, batch, dtype == HARP_C64 ? 8 : 16)) return HARP_E_WORKSPACE;
+    harp_status s;
+    if (dtype == HARP_C64) {
+        float* A = static_cast<float*>(d_A);
+        if ((s = factor_impl<float>(n, batch, A, lda, stride_a, d_ipiv, d_info, stream)) != HARP_OK) return s;
+        return tri_inverse<float>(n, batch, A, lda, stride_a, d_ipiv, static_cast<float*>(d_aux), stream);
+    }
+    double* A = static_cast<double*>(d_A);
+    if ((s = factor_impl<double>(n, batch, A, lda, stride_a, d_ipiv, d_info, stream)) != HARP_OK) return s;
+    return tri_inverse<double>(n, batch, A, lda, stride_a, d_ipiv, static_cast<double*>(d_aux), stream);
 }
 
 extern "C" harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, int32_t refine,
@@ -798,12 +1045,14 @@ extern "C" harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, 
 }
 
 extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, const void* d_LU,
-                                     int64_t lda, int64_t stride_lu, const int32_t* d_ipiv, const void* d_B,
+                                     int64_t lda, int64_t stride_lu, const int32_t* d_ipiv, const void* d_aux,
+                                     size_t aux_size, const void* d_B,
                                      int64_t ldb, int64_t stride_b, void* d_X, int64_t ldx, int64_t stride_x,
                                      const harp_refine* refine, harp_refine_report* report, void* d_ws,
                                      size_t ws_bytes, hipStream_t st) {
     if (!d_LU || !d_ipiv || !d_B || !d_X || n <= 0 || nrhs <= 0 || batch <= 0 || batch > 65535) return HARP_E_ARG;
     if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
+    if (!d_aux || aux_size < aux_bytes(n, batch, dtype == HARP_C64 ? 8 : 16)) return HARP_E_WORKSPACE;
     if (lda < n || ldb < n || ldx < n) return HARP_E_ARG;
     if (batch > 1 && (stride_lu < lda * n || stride_b < ldb * nrhs || stride_x < ldx * nrhs)) return HARP_E_ARG;
     const bool ref = refine != nullptr;
@@ -818,30 +1067,46 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
     const int64_t mat = int64_t(n) * nrhs;
     harp_status s;
 
-    // first solve in the factor precision, result promoted into X
-    auto solve_into = [&](const void* rhs, int64_t ldr, int64_t sr, const int32_t* active, bool accumulate) {
+    // solve in the factor precision; the result is written into X, or added
+    // to X (corrections)
+    auto solve_into = [&](const void* rhs, int64_t ldr, int64_t sr, const int32_t* act,
+                          bool accumulate) -> harp_status {
+        harp_status q;
+        double2* Xd = static_cast<double2*>(d_X);
+        const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
         if (dtype == HARP_C64) {
-            if ((s = convert<double2, float2>(rhs, ldr, sr, W.B32, n, mat, n, nrhs, batch, active, st)) != HARP_OK)
-                return s;
-            if ((s = solve_impl<float>(n, nrhs, batch, static_cast<const float*>(d_LU), lda, stride_lu, d_ipiv,
-                                       reinterpret_cast<float*>(W.B32), n, mat, active, st)) != HARP_OK)
-                return s;
+            const float* LU = static_cast<const float*>(d_LU);
+            if ((q = convert<double2, float2>(rhs, ldr, sr, W.B32, n, mat, n, nrhs, batch, act, st)) != HARP_OK)
+                return q;
+            if ((q = solve_impl<float>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const float*>(d_aux),
+                                       reinterpret_cast<float*>(W.B32), n, mat, static_cast<float*>(W.Tm), act,
+                                       st)) != HARP_OK)
+                return q;
             if (accumulate) {
-                const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
                 HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                                 hipLaunchKernelGGL(axpy_kernel<float2>, dim3(blocks, 1, batch), dim3(256), 0, st,
-                                                    static_cast<double2*>(d_X), ldx, stride_x, W.B32, n, mat, n,
-                                                    nrhs, active));
+                                 hipLaunchKernelGGL(axpy_kernel<float2>, dim3(blocks, 1, batch), dim3(256), 0, st, Xd,
+                                                    ldx, stride_x, W.B32, n, mat, n, nrhs, act));
                 HARP_LAUNCH_CHECK();
                 return HARP_OK;
             }
-            return convert<float2, double2>(W.B32, n, mat, d_X, ldx, stride_x, n, nrhs, batch, active, st);
+            return convert<float2, double2>(W.B32, n, mat, Xd, ldx, stride_x, n, nrhs, batch, act, st);
         }
-        // complex128 factors: solve directly in X (corrections take the branch in the loop)
-        if ((s = convert<double2, double2>(rhs, ldr, sr, d_X, ldx, stride_x, n, nrhs, batch, active, st)) != HARP_OK)
-            return s;
-        return solve_impl<double>(n, nrhs, batch, static_cast<const double*>(d_LU), lda, stride_lu, d_ipiv,
-                                  static_cast<double*>(d_X), ldx, stride_x, active, st);
+        const double* LU = static_cast<const double*>(d_LU);
+        if (accumulate) {   // rhs is the residual W.R: solve it in place, then add
+            if ((q = solve_impl<double>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const double*>(d_aux),
+                                        reinterpret_cast<double*>(W.R), n, mat, static_cast<double*>(W.Tm), act,
+                                        st)) != HARP_OK)
+                return q;
+            HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                             hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st, Xd,
+                                                ldx, stride_x, W.R, n, mat, n, nrhs, act));
+            HARP_LAUNCH_CHECK();
+            return HARP_OK;
+        }
+        if ((q = convert<double2, double2>(rhs, ldr, sr, Xd, ldx, stride_x, n, nrhs, batch, act, st)) != HARP_OK)
+            return q;
+        return solve_impl<double>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const double*>(d_aux),
+                                  reinterpret_cast<double*>(Xd), ldx, stride_x, static_cast<double*>(W.Tm), act, st);
     };
 
     if ((s = solve_into(d_B, ldb, stride_b, nullptr, false)) != HARP_OK) return s;
@@ -898,19 +1163,7 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
         if (n_active == 0) break;
         HARP_HIP_CHECK(hipMemcpyAsync(W.active, act.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
         // correction: D = LU^-1 R, X += D
-        if (dtype == HARP_C64) {
-            if ((s = solve_into(W.R, n, mat, W.active, true)) != HARP_OK) return s;
-        } else {
-            if ((s = solve_impl<double>(n, nrhs, batch, static_cast<const double*>(d_LU), lda, stride_lu, d_ipiv,
-                                        reinterpret_cast<double*>(W.R), n, mat, W.active, st)) != HARP_OK)
-                return s;
-            const unsigned blocks = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
-            HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                             hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st,
-                                                static_cast<double2*>(d_X), ldx, stride_x, W.R, n, mat, n, nrhs,
-                                                W.active));
-            HARP_LAUNCH_CHECK();
-        }
+        if ((s = solve_into(W.R, n, mat, W.active, true)) != HARP_OK) return s;
         for (int b = 0; b < batch; ++b) iters[b] += act[b];
         // make sure the host vectors are not reused before the copies finish
         HARP_HIP_CHECK(hipStreamSynchronize(st));

@@ -65,7 +65,8 @@ def test_cgemm_hook(api, dt, shape):
 
 
 @pytest.mark.parametrize("dt,n,batch", [("c128", 70, 2), ("c128", 300, 3), ("c64", 111, 2),
-                                        ("c64", 257, 3), ("c128", 64, 1), ("c64", 1, 2)])
+                                        ("c64", 257, 3), ("c128", 64, 1), ("c64", 1, 2),
+                                        ("c64", 700, 2), ("c128", 513, 2)])
 def test_factor_and_solve_random(api, dt, n, batch):
     """Diagonally weighted random systems (ragged block sizes): solve vs LAPACK;
     the complex64 factors with FP64 refinement reach the FP64 solution."""
@@ -73,9 +74,10 @@ def test_factor_and_solve_random(api, dt, n, batch):
     Bh = _rand((batch, n, 5), 20 + n)
     tdt = torch.complex64 if dt == "c64" else torch.complex128
     LU = _to_cm(api, A.astype(np.complex64 if dt == "c64" else np.complex128), tdt)
-    ipiv, info = api.reduced_factor(LU)
+    F = api.reduced_factor(LU)
+    info = F.info
     B = _to_cm(api, Bh, torch.complex128)
-    X, _ = api.reduced_solve(LU, ipiv, B)
+    X, _ = api.reduced_solve(F, B)
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all()
     ref = np.linalg.solve(A, Bh)
@@ -83,7 +85,7 @@ def test_factor_and_solve_random(api, dt, n, batch):
     assert err <= (1e-5 if dt == "c64" else 1e-12), err
     if dt == "c64":
         Z64 = _to_cm(api, A, torch.complex128)
-        X2, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-13, max_iter=10)
+        X2, rep = api.reduced_solve(F, B, Z64=Z64, tol=1e-13, max_iter=10)
         torch.cuda.synchronize()
         err2 = np.linalg.norm(X2.cpu().numpy() - ref) / np.linalg.norm(ref)
         assert err2 <= 1e-11, (err2, rep)
@@ -120,16 +122,16 @@ def test_refinement_report_and_noconv(api):
     n = 96
     A = _rand((1, n, n), 8) + 3 * np.sqrt(n) * np.eye(n)[None]
     LU = _to_cm(api, A.astype(np.complex64), torch.complex64)
-    ipiv, _ = api.reduced_factor(LU)
+    F = api.reduced_factor(LU)
     B = _to_cm(api, _rand((1, n, 4), 9), torch.complex128)
     Z64 = _to_cm(api, A, torch.complex128)
     from paper_1702_03781_amd._lib import HarpError
     with pytest.raises(HarpError) as e:
-        api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-300, max_iter=0)
+        api.reduced_solve(F, B, Z64=Z64, tol=1e-300, max_iter=0)
     assert e.value.status == -4
-    X, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-300, max_iter=0, raise_noconv=False)
+    X, rep = api.reduced_solve(F, B, Z64=Z64, tol=1e-300, max_iter=0, raise_noconv=False)
     assert rep[0]["iters"] == 0 and not rep[0]["converged"]
-    X, rep = api.reduced_solve(LU, ipiv, B, Z64=Z64, tol=1e-12, max_iter=5)
+    X, rep = api.reduced_solve(F, B, Z64=Z64, tol=1e-12, max_iter=5)
     assert rep[0]["converged"] and 1 <= rep[0]["iters"] <= 5 and rep[0]["resid_rel"] <= 1e-12
 
 
@@ -141,12 +143,14 @@ def _pipeline(api, models_o, x, y, refined=True):
     B = api.harp_port_rhs(mb, n_ant)
     if refined:
         Z64, Z32, info = api.harp_fill(mb, xt, yt, dtype="c128", dual=True)
-        ipiv, finfo = api.reduced_factor(Z32)
-        X, rep = api.reduced_solve(Z32, ipiv, B, Z64=Z64, tol=1e-10, max_iter=10)
+        F = api.reduced_factor(Z32)
+        finfo = F.info
+        X, rep = api.reduced_solve(F, B, Z64=Z64, tol=1e-10, max_iter=10)
     else:
         Z64, _, info = api.harp_fill(mb, xt, yt, dtype="c128")
-        ipiv, finfo = api.reduced_factor(Z64)
-        X, rep = api.reduced_solve(Z64, ipiv, B)
+        F = api.reduced_factor(Z64)
+        finfo = F.info
+        X, rep = api.reduced_solve(F, B)
     Y = api.harp_port_admittance(mb, X)
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all() and (finfo.cpu().numpy() == 0).all()
