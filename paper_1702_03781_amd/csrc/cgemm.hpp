@@ -19,10 +19,16 @@
 // and B~[l/16][l%16] and receives four entries of column l%16 of C~ (rows
 // 4(l/16)+v for the f32 form, 4v+l/16 for the f64 form, v = 0..3).
 //
-// Tiling: 256 threads = 2 x 2 waves; workgroup tile BM complex rows x BN
-// columns, K streamed in BK-wide complex chunks through double-buffered LDS
-// (A chunk stored [k][row], B chunk [col][k] padded by one complex to spread
-// banks).  Each wave owns (BM/2) x (BN/2): (BM/16) x (BN/32) MFMA blocks.
+// Tiling: 256 threads = WM x WN waves over a BM x BN complex workgroup tile;
+// K streamed in BK-wide complex chunks through double-buffered LDS (A chunk
+// stored [k][row] with its k-rows 16 banks apart, B chunk [col][k] with
+// 16-byte aligned columns).  Global loads and the f32 C/D accesses move 16
+// bytes per lane (two complex64 or one complex128) when the operands are
+// aligned; each lane reads from LDS only the real component it feeds; the
+// register fragments of the next MFMA step are read while the current step's
+// MFMAs issue.  Each wave owns (BM/WM) x (BN/WN): (BM/WM/8) x (BN/WN/16)
+// MFMA blocks.  Small, register-light tiles keep four waves per SIMD, which
+// on this hardware beats larger tiles for the rank-64 LU updates.
 #pragma once
 
 #include "common.hpp"
@@ -71,16 +77,25 @@ template <typename T> struct GemmArgs {
     int64_t sA2 = 0, sB2 = 0, sC2 = 0, sD2 = 0;
 };
 
-template <typename T, int BM, int BN, int BK>
+template <typename T> struct alignas(16) Vec16 {
+    typename Mfma<T>::c_t v[16 / sizeof(typename Mfma<T>::c_t)];
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC>
 __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
     using ct = typename Mfma<T>::c_t;
     using acc_t = typename Mfma<T>::acc_t;
-    constexpr int RB = BM / 16;          // MFMA row blocks per wave (8 complex rows each)
-    constexpr int CB = BN / 32;          // MFMA column blocks per wave (16 columns each)
-    constexpr int A_PER_T = BM * BK / 256;
-    constexpr int B_PER_T = BN * BK / 256;
-    static_assert(BM % 16 == 0 && BN % 32 == 0 && BK % 2 == 0, "tile shape");
-    static_assert(A_PER_T >= 1 && B_PER_T >= 1, "tile too small for 256 threads");
+    constexpr int NV = int(16 / sizeof(ct));          // complex per 16-byte access
+    constexpr int WTM = BM / WM, WTN = BN / WN;       // wave tile
+    constexpr int RB = WTM / 8, CB = WTN / 16;        // MFMA blocks per wave
+    constexpr int NA = BM * BK / NV / 256;            // A vectors per thread per chunk
+    constexpr int NBv = BN * BK / NV / 256;           // B vectors per thread per chunk
+    constexpr int APAD = 8 / (int(sizeof(ct)) / 8);   // k-row stride = 16 banks mod 64
+    constexpr int BPAD = NV;                          // keeps B columns 16-byte aligned
+    constexpr int KS = BK / 2;                        // MFMA steps per chunk
+    static_assert(WM * WN == 4, "four waves");
+    static_assert(WTM % 8 == 0 && WTN % 16 == 0 && BK % NV == 0 && BK % 2 == 0, "tile shape");
+    static_assert(NA >= 1 && NBv >= 1 && NA * NV * 256 == BM * BK && NBv * NV * 256 == BN * BK, "load split");
 
     const int bz = blockIdx.z / g.inner, bi = blockIdx.z % g.inner;
     if (g.active && g.active[bz] == 0) return;
@@ -91,107 +106,138 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
     const ct* A = reinterpret_cast<const ct*>(g.A) + size_t(bz) * g.sA + size_t(bi) * g.sA2;
     const ct* B = reinterpret_cast<const ct*>(g.B) + size_t(bz) * g.sB + size_t(bi) * g.sB2;
 
-    __shared__ ct As[2][BK][BM];
-    __shared__ ct Bs[2][BN][BK + 1];
+    __shared__ __attribute__((aligned(16))) ct As[2][BK][BM + APAD];
+    __shared__ __attribute__((aligned(16))) ct Bs[2][BN][BK + BPAD];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave & 1) * (BM / 2);    // wave's complex-row offset in the tile
-    const int wc = (wave >> 1) * (BN / 2);   // wave's column offset in the tile
+    const int wr = (wave % WM) * WTM;
+    const int wc = (wave / WM) * WTN;
 
-    // global -> register staging
-    ct ra[A_PER_T], rb[B_PER_T];
-    // A chunk: thread owns k = tid / (BM / A_PER_T), rows (tid % (BM / A_PER_T)) * A_PER_T + e
-    constexpr int A_ROW_GROUPS = BM / A_PER_T;
-    const int a_k = tid / A_ROW_GROUPS, a_r = (tid % A_ROW_GROUPS) * A_PER_T;
-    // B chunk: thread owns column tid / (BK / B_PER_T), k (tid % (BK / B_PER_T)) * B_PER_T + e
-    constexpr int B_K_GROUPS = BK / B_PER_T;
-    const int b_c = tid / B_K_GROUPS, b_k = (tid % B_K_GROUPS) * B_PER_T;
-
+    // global -> registers: A vector e covers rows a_r[e]..+NV-1 of k-row a_k[e];
+    // B vector e covers k b_k[e]..+NV-1 of column b_c[e]
+    Vec16<T> ra[NA], rb[NBv];
     auto load_chunk = [&](int k0) {
-        const int ka = k0 + a_k;
 #pragma unroll
-        for (int e = 0; e < A_PER_T; ++e) {
-            const int r = row0 + a_r + e;
-            ra[e] = (r < g.M && ka < g.K) ? A[size_t(ka) * g.lda + r] : ct{T(0), T(0)};
+        for (int e = 0; e < NA; ++e) {
+            const int v = tid + 256 * e;
+            const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
+            const int gk = k0 + kk, gr = row0 + r;
+            const ct* src = A + size_t(gk) * g.lda + gr;
+            if (VEC && gk < g.K && gr + NV <= g.M) {
+                ra[e] = *reinterpret_cast<const Vec16<T>*>(src);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+                    ra[e].v[q] = (gk < g.K && gr + q < g.M) ? src[q] : ct{T(0), T(0)};
+            }
         }
-        const int cb = col0 + b_c;
 #pragma unroll
-        for (int e = 0; e < B_PER_T; ++e) {
-            const int kb = k0 + b_k + e;
-            rb[e] = (cb < g.N && kb < g.K) ? B[size_t(cb) * g.ldb + kb] : ct{T(0), T(0)};
+        for (int e = 0; e < NBv; ++e) {
+            const int v = tid + 256 * e;
+            const int c = v / (BK / NV), kk = (v % (BK / NV)) * NV;
+            const int gc = col0 + c, gk = k0 + kk;
+            const ct* src = B + size_t(gc) * g.ldb + gk;
+            if (VEC && gc < g.N && gk + NV <= g.K) {
+                rb[e] = *reinterpret_cast<const Vec16<T>*>(src);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+                    rb[e].v[q] = (gc < g.N && gk + q < g.K) ? src[q] : ct{T(0), T(0)};
+            }
         }
     };
     auto store_chunk = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < A_PER_T; ++e) As[buf][a_k][a_r + e] = ra[e];
+        for (int e = 0; e < NA; ++e) {
+            const int v = tid + 256 * e;
+            const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
+            *reinterpret_cast<Vec16<T>*>(&As[buf][kk][r]) = ra[e];
+        }
 #pragma unroll
-        for (int e = 0; e < B_PER_T; ++e) Bs[buf][b_c][b_k + e] = rb[e];
+        for (int e = 0; e < NBv; ++e) {
+            const int v = tid + 256 * e;
+            const int c = v / (BK / NV), kk = (v % (BK / NV)) * NV;
+            *reinterpret_cast<Vec16<T>*>(&Bs[buf][c][kk]) = rb[e];
+        }
     };
 
-    // accumulators start at beta * C (read before the K loop so its latency
-    // overlaps the first A/B chunk); alpha is folded into the A operand
+    // accumulators start at beta * C; f32 outputs of a lane are four
+    // consecutive real rows (one 16-byte access when aligned and in range)
     const int b_col = lane & 15;
     const int M2 = 2 * g.M;
     acc_t acc[RB][CB];
     {
         const T* Cr = g.C ? g.C + 2 * (size_t(bz) * g.sC + size_t(bi) * g.sC2) : nullptr;
+        const bool use_c = g.beta != T(0) && Cr != nullptr;
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int col = col0 + wc + j * 16 + b_col;
                 const int rbase = 2 * (row0 + wr + i * 8);
+                acc[i][j] = acc_t{T(0), T(0), T(0), T(0)};
+                if (!use_c || col >= g.N) continue;
+                const T* cp = Cr + 2 * size_t(col) * g.ldc;
+                if constexpr (sizeof(T) == 4) {
+                    const int r4 = rbase + 4 * (lane >> 4);
+                    if (VEC && r4 + 4 <= M2) {
+                        const f32x4 c4 = *reinterpret_cast<const f32x4*>(cp + r4);
+                        acc[i][j] = c4 * g.beta;
+                        continue;
+                    }
+                }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int rr = rbase + Mfma<T>::out_row(lane, v);
-                    acc[i][j][v] = (g.beta != T(0) && col < g.N && rr < M2)
-                                       ? g.beta * Cr[2 * size_t(col) * g.ldc + rr]
-                                       : T(0);
+                    if (rr < M2) acc[i][j][v] = g.beta * cp[rr];
                 }
             }
     }
 
     // operand selection for this lane (see the header comment)
-    const int s = lane & 1;                  // real row parity: 0 = re row, 1 = im row
-    const int u = (lane >> 4) & 1;           // real k parity:   0 = re k,   1 = im k
-    const int kq = lane >> 5;                // which of the 2 complex k of an MFMA step
+    const int s = lane & 1;
+    const int u = (lane >> 4) & 1;
+    const int kq = lane >> 5;
     const bool take_im_a = (s ^ u) != 0;
     const T sign_a = ((s == 0 && u == 1) ? T(-1) : T(1)) * g.alpha;
-    const int a_row = (lane & 15) >> 1;      // complex row within an 8-row block
+    const int a_row = (lane & 15) >> 1;
+
+    // each lane reads only the component it feeds (half the LDS traffic of
+    // reading whole complex numbers)
+    T fa[2][RB], fb[2][CB];
+    const int a_part = take_im_a ? 1 : 0;
+    auto frag = [&](int buf, int step, T (&av)[RB], T (&bv)[CB]) {
+        const int k = 2 * step + kq;
+        const T* ap = reinterpret_cast<const T*>(&As[buf][k][wr + a_row]) + a_part;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) av[i] = sign_a * ap[2 * 8 * i];
+#pragma unroll
+        for (int j = 0; j < CB; ++j) bv[j] = reinterpret_cast<const T*>(&Bs[buf][wc + j * 16 + b_col][k])[u];
+    };
 
     const int nchunks = (g.K + BK - 1) / BK;
-    load_chunk(0);
-    store_chunk(0);
+    if (nchunks > 0) {
+        load_chunk(0);
+        store_chunk(0);
+    }
     __syncthreads();
     for (int c = 0; c < nchunks; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunks) load_chunk((c + 1) * BK);
+        frag(buf, 0, fa[0], fb[0]);
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 2) {
-            const int k = kk + kq;
-            T av[RB], bv[CB];
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const ct a = As[buf][k][wr + i * 8 + a_row];
-                av[i] = sign_a * (take_im_a ? a.y : a.x);
-            }
-#pragma unroll
-            for (int j = 0; j < CB; ++j) {
-                const ct b = Bs[buf][wc + j * 16 + b_col][k];
-                bv[j] = u ? b.y : b.x;
-            }
+        for (int st = 0; st < KS; ++st) {
+            if (st + 1 < KS) frag(buf, st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
 #pragma unroll
             for (int i = 0; i < RB; ++i)
 #pragma unroll
-                for (int j = 0; j < CB; ++j) acc[i][j] = Mfma<T>::op(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < CB; ++j) acc[i][j] = Mfma<T>::op(fa[st & 1][i], fb[st & 1][j], acc[i][j]);
         }
         if (c + 1 < nchunks) store_chunk(buf ^ 1);
         __syncthreads();
     }
 
-    // epilogue in the real view of the interleaved storage: real row 2i + part
-    // is exactly the MFMA output row
     T* Dr = g.D + 2 * (size_t(bz) * g.sD + size_t(bi) * g.sD2);
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
@@ -200,39 +246,58 @@ __global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
             const int col = col0 + wc + j * 16 + b_col;
             if (col >= g.N) continue;
             const int rbase = 2 * (row0 + wr + i * 8);
+            T* dp = Dr + 2 * size_t(col) * g.ldd;
+            if constexpr (sizeof(T) == 4) {
+                const int r4 = rbase + 4 * (lane >> 4);
+                if (VEC && r4 + 4 <= M2) {
+                    *reinterpret_cast<f32x4*>(dp + r4) = acc[i][j];
+                    continue;
+                }
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int rr = rbase + Mfma<T>::out_row(lane, v);
-                if (rr < M2) Dr[2 * size_t(col) * g.ldd + rr] = acc[i][j][v];
+                if (rr < M2) dp[rr] = acc[i][j][v];
             }
         }
     }
 }
 
-template <typename T> struct GemmTile;
-template <> struct GemmTile<float> {
-    static constexpr int BM = 64, BN = 64, BK = 16;
-};
-template <> struct GemmTile<double> {
-    static constexpr int BM = 32, BN = 64, BK = 16;
-};
+// true when every operand row start is 16-byte aligned (pointers, leading
+// dimensions and batch strides), so the vector paths of cgemm_kernel apply
+template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
+    constexpr int64_t NV = 16 / (2 * sizeof(T));
+    auto al = [](const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    auto ev = [](int64_t x) { return x % NV == 0; };
+    return al(g.A) && al(g.B) && al(g.C) && al(g.D) && ev(g.lda) && ev(g.ldb) && ev(g.ldc) && ev(g.ldd) &&
+           ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream) {
+    const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
+    if (gemm_vec_ok(g))
+        hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, true>), grid, dim3(256), 0, stream, g);
+    else
+        hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, false>), grid, dim3(256), 0, stream, g);
+}
 
 // Enqueue D = beta C + alpha A B for `batch` (x g.inner) matrices.  M, N, K
 // may be zero.  eff_batch (< 0: batch) is the number of outer matrices not
 // skipped by g.active, used only for the work accounting of the profiler.
+// Narrow products (N <= 32: the LU's in-block updates, few right-hand sides)
+// take the 64 x 32 tile, everything else 64 x 64 (four waves stacked on rows).
 template <typename T>
 inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
     if (g.M <= 0 || g.N <= 0 || batch <= 0 || g.inner <= 0) return HARP_OK;
     if (int64_t(batch) * g.inner > 65535) return HARP_E_ARG;
-    constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN, BK = GemmTile<T>::BK;
-    const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     // K == 0 runs the same kernel with an empty contraction: D = beta C
     const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
     HARP_PROF_LAUNCH(sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64, stream,
                      8.0 * double(g.M) * double(g.N) * double(g.K) * nb, 0.0,
-                     hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK>),
-                                        dim3(unsigned(tiles), 1u, unsigned(batch * g.inner)), dim3(256), 0, stream,
-                                        g));
+                     (g.N <= 32 ? launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream)
+                                : launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream)));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }

@@ -23,6 +23,7 @@
 // the same order, which is equivalent (the multipliers of block K are stored
 // in the row order current at step K).
 #include <float.h>
+#include <limits.h>
 #include <math.h>
 
 #include <algorithm>
@@ -93,25 +94,159 @@ __device__ inline double readlane_v(double v, int l) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 template <typename T> __device__ inline void take_if_better(T ov, int oi, T& best, int& bidx) {
-    if (ov > best || (ov == best && oi < bidx)) {
-        best = ov;
-        bidx = oi;
-    }
+    // branch-free: the selects stay in VALU without exec-mask changes
+    const bool t = (ov > best) | ((ov == best) & (oi < bidx));
+    best = t ? ov : best;
+    bidx = t ? oi : bidx;
 }
 template <typename T, int CTRL> __device__ inline void dpp_step(T& best, int& bidx) {
     take_if_better(dpp_v<CTRL>(best), dpp_i<CTRL>(bidx), best, bidx);
 }
-template <typename T> __device__ inline void wave_argmax(T& best, int& bidx) {
+template <typename T> __device__ inline void row16_argmax(T& best, int& bidx) {
     dpp_step<T, 0xB1>(best, bidx);    // quad_perm [1,0,3,2]
     dpp_step<T, 0x4E>(best, bidx);    // quad_perm [2,3,0,1]
     dpp_step<T, 0x124>(best, bidx);   // row_ror:4
     dpp_step<T, 0x128>(best, bidx);   // row_ror:8
-    T b = readlane_v(best, 0);
-    int i = __builtin_amdgcn_readlane(bidx, 0);
+}
+// row broadcasts: lane 15 of each row into the next row (rows 1 and 3), then
+// lane 31 into rows 2 and 3; lane 63 ends with the wave's result.  Rows left
+// out by the row mask compare their value with itself (no change).
+template <int CTRL, int ROWS> __device__ inline int dpp_rows_i(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS> __device__ inline float dpp_rows_v(float old, float v) {
+    return __int_as_float(dpp_rows_i<CTRL, ROWS>(__float_as_int(old), __float_as_int(v)));
+}
+template <int CTRL, int ROWS> __device__ inline double dpp_rows_v(double old, double v) {
+    const long long o = __double_as_longlong(old), b = __double_as_longlong(v);
+    const int lo = dpp_rows_i<CTRL, ROWS>(int(o), int(b)), hi = dpp_rows_i<CTRL, ROWS>(int(o >> 32), int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <typename T, int CTRL, int ROWS> __device__ inline void dpp_bcast_step(T& best, int& bidx) {
+    take_if_better(dpp_rows_v<CTRL, ROWS>(best, best), dpp_rows_i<CTRL, ROWS>(bidx, bidx), best, bidx);
+}
+template <typename T> __device__ inline void wave_argmax(T& best, int& bidx) {
+    row16_argmax(best, bidx);
+    dpp_bcast_step<T, 0x142, 0xA>(best, bidx);   // row_bcast:15
+    dpp_bcast_step<T, 0x143, 0xC>(best, bidx);   // row_bcast:31
+    best = readlane_v(best, 63);
+    bidx = __builtin_amdgcn_readlane(bidx, 63);
+}
+
+// Reciprocal of a pivot.  Single precision: Smith's scaling with the hardware
+// reciprocal (about 1 ulp per step; the refinement absorbs it).  Double
+// precision: IEEE divisions.
+__device__ inline float2 crecip_pivot(float2 a) {
+    if (fabsf(a.x) >= fabsf(a.y)) {
+        const float r = a.y * __builtin_amdgcn_rcpf(a.x), d = fmaf(a.y, r, a.x);
+        const float id = __builtin_amdgcn_rcpf(d);
+        return float2{id, -r * id};
+    }
+    const float r = a.x * __builtin_amdgcn_rcpf(a.y), d = fmaf(a.x, r, a.y);
+    const float id = __builtin_amdgcn_rcpf(d);
+    return float2{r * id, -id};
+}
+__device__ inline double2 crecip_pivot(double2 a) { return crecip(a); }
+
+// LDS of the panel kernel (candidates double-buffered by column parity)
+template <typename T, int NT, int W> struct PanelShared {
+    using V = typename C2<T>::t;
+    static constexpr int NW = NT / 64;
+    T cand_v[2][NW];
+    int cand_i[2][NW];
+    V cand_row[2][NW][W];
+    V jrow[2][W];
+    V Ls[W][W];
+    int piv_s[W];
+    int cand_s[2 * W], src_s[2 * W];
+    V stage[NBMAX - W][2 * W];
+};
+
+// Column JJ of the panel (then JJ+1, ...): a compile-time recursion, so the
+// register-resident panel is only ever indexed by constants.
+template <typename T, int NT, int RPT, int W, int JJ>
+__device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], PanelShared<T, NT, W>& sh,
+                                              const PanelArgs& pa, int b, int tid) {
+    if constexpr (JJ < W) {
+        using V = typename C2<T>::t;
+        constexpr int NW = NT / 64;
+        constexpr int par = JJ & 1;
+        const int j0 = pa.j0, n = pa.n;
+        if (JJ >= pa.w) return;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int j = j0 + JJ;
+        // local candidate: rows outside [j, n) carry -2 and never win; a NaN
+        // never wins a comparison; bidx stays j when no row qualifies
+        T best = T(-1);
+        int bidx = j;
 #pragma unroll
-    for (int r = 16; r < 64; r += 16) take_if_better(readlane_v(best, r), __builtin_amdgcn_readlane(bidx, r), b, i);
-    best = b;
-    bidx = i;
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            const T m = fabs(a[r][JJ].x) + fabs(a[r][JJ].y);
+            take_if_better((row >= j && row < n) ? m : T(-2), row, best, bidx);
+        }
+        wave_argmax(best, bidx);
+        // the owner of the wave's best row publishes it; the owner of row j publishes row j
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            if (row == bidx) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) sh.cand_row[par][wave][c] = a[r][c];
+            }
+            if (row == j) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) sh.jrow[par][c] = a[r][c];
+            }
+        }
+        if (lane == 0) {
+            sh.cand_v[par][wave] = best;
+            sh.cand_i[par][wave] = bidx;
+        }
+        __syncthreads();
+        // every wave reduces the NW candidates at once (lane q holds wave q's);
+        // the winner was published by the wave that owns its row
+        best = T(-1);
+        bidx = INT_MAX;
+        if (lane < NW) {
+            best = sh.cand_v[par][lane];
+            bidx = sh.cand_i[par][lane];
+        }
+        row16_argmax(best, bidx);
+        best = readlane_v(best, 0);
+        const int p = __builtin_amdgcn_readlane(bidx, 0);
+        const int wb = ((p - j0) % NT) >> 6;
+        if (tid == 0) {
+            sh.piv_s[JJ] = p;
+            pa.ipiv[size_t(b) * n + j] = p;
+            if (best == T(0)) atomicCAS(pa.info + b, 0, j + 1);
+        }
+        // a zero pivot leaves the column as it is (its entries below are zero)
+        const V inv = best != T(0) ? crecip_pivot(sh.cand_row[par][wb][JJ]) : V{T(0), T(0)};
+        V l[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int row = j0 + tid + r * NT;
+            if (p != j && row == j) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[r][c] = sh.cand_row[par][wb][c];
+            } else if (p != j && row == p) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) a[r][c] = sh.jrow[par][c];
+            }
+            // multipliers below the diagonal; zero above it (no update there)
+            l[r] = row > j ? cm(a[r][JJ], inv) : V{T(0), T(0)};
+            if (row > j) a[r][JJ] = l[r];
+        }
+        // rank-1 update, one pivot-row entry at a time (columns past w are zero)
+#pragma unroll
+        for (int c = JJ + 1; c < W; ++c) {
+            const V u = sh.cand_row[par][wb][c];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) a[r][c] = cfms(a[r][c], l[r], u);
+        }
+        panel_columns<T, NT, RPT, W, JJ + 1>(a, sh, pa, b, tid);
+    }
 }
 
 // One workgroup per matrix factors rows [j0, n) x columns [j0, j0+w) held in
@@ -123,20 +258,19 @@ template <typename T, int NT, int RPT, int W>
 __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     using V = typename C2<T>::t;
     constexpr int NW = NT / 64;
+    static_assert(NW <= 16, "candidates are reduced within one 16-lane row");
     const int b = blockIdx.x;
     V* A = reinterpret_cast<V*>(pa.A) + size_t(b) * pa.sA;
     const int64_t lda = pa.lda;
     const int n = pa.n, j0 = pa.j0, w = pa.w;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
 
-    __shared__ T cand_v[2][NW];
-    __shared__ int cand_i[2][NW];
-    __shared__ V cand_row[2][NW][W];
-    __shared__ V jrow[2][W];
-    __shared__ V Ls[W][W];
-    __shared__ int piv_s[W];
-    __shared__ int cand_s[2 * W], src_s[2 * W];
-    __shared__ V stage[NBMAX - W][2 * W];
+    __shared__ PanelShared<T, NT, W> sh;
+    auto& Ls = sh.Ls;
+    auto& piv_s = sh.piv_s;
+    auto& cand_s = sh.cand_s;
+    auto& src_s = sh.src_s;
+    auto& stage = sh.stage;
 
     V a[RPT][W];
 #pragma unroll
@@ -147,78 +281,7 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
             a[r][c] = (row < n && c < w) ? A[size_t(j0 + c) * lda + row] : V{T(0), T(0)};
     }
 
-#pragma unroll
-    for (int jj = 0; jj < W; ++jj) {
-        if (jj >= w) break;
-        const int par = jj & 1;
-        const int j = j0 + jj;
-        T best = T(-1);
-        int bidx = j;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            const T m = fabs(a[r][jj].x) + fabs(a[r][jj].y);
-            if (row >= j && row < n) take_if_better(m, row, best, bidx);
-        }
-        wave_argmax(best, bidx);
-        // the owner of the wave's best row publishes it; the owner of row j publishes row j
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            if (row == bidx) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) cand_row[par][wave][c] = a[r][c];
-            }
-            if (row == j) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) jrow[par][c] = a[r][c];
-            }
-        }
-        if (lane == 0) {
-            cand_v[par][wave] = best;
-            cand_i[par][wave] = bidx;
-        }
-        __syncthreads();
-        int wb = 0;
-        best = cand_v[par][0];
-        bidx = cand_i[par][0];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) {
-            const T ob = cand_v[par][q];
-            const int oi = cand_i[par][q];
-            if (ob > best || (ob == best && oi < bidx)) {
-                best = ob;
-                bidx = oi;
-                wb = q;
-            }
-        }
-        const int p = bidx;
-        if (tid == 0) {
-            piv_s[jj] = p;
-            pa.ipiv[size_t(b) * n + j] = p;
-            if (best == T(0)) atomicCAS(pa.info + b, 0, j + 1);
-        }
-        const bool nz = best != T(0);
-        const V inv = nz ? crecip(cand_row[par][wb][jj]) : V{T(0), T(0)};
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            if (p != j && row == j) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) a[r][c] = cand_row[par][wb][c];
-            } else if (p != j && row == p) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) a[r][c] = jrow[par][c];
-            }
-            if (row > j && row < n && nz) {
-                const V l = cm(a[r][jj], inv);
-                a[r][jj] = l;
-#pragma unroll
-                for (int c = jj + 1; c < W; ++c)
-                    if (c < w) a[r][c] = cfms(a[r][c], l, cand_row[par][wb][c]);
-            }
-        }
-    }
+    panel_columns<T, NT, RPT, W, 0>(a, sh, pa, b, tid);
     __syncthreads();
 
     // write the panel back; keep its unit-lower top block in LDS
@@ -270,18 +333,21 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
         A[size_t(col) * lda + r] = stage[oc][t];
     }
     // unit-lower solve of the top rows of the right columns
-    for (int oc = left + tid; oc < nother; oc += NT) {
+    // (one column per thread: the outer block is narrower than the workgroup,
+    // and a single pass keeps the LDS reads of Ls out of any loop)
+    static_assert(NBMAX <= NT, "one thread per column of the outer block");
+    if (const int oc = left + tid; oc < nother) {
         const int col = j0 + w + (oc - left);
         V x[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) x[i] = i < w ? stage[oc][i] : V{T(0), T(0)};
+        // column-oriented substitution: x[q] is final once reached
 #pragma unroll
-        for (int i = 1; i < W; ++i)
+        for (int q = 0; q < W; ++q) {
+            if (q < w) A[size_t(col) * lda + j0 + q] = x[q];
 #pragma unroll
-            for (int q = 0; q < i; ++q) x[i] = cfms(x[i], Ls[i][q], x[q]);
-#pragma unroll
-        for (int i = 0; i < W; ++i)
-            if (i < w) A[size_t(col) * lda + j0 + i] = x[i];
+            for (int i = q + 1; i < W; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
+        }
     }
 }
 
