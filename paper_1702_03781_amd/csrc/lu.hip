@@ -148,112 +148,204 @@ __device__ inline float2 crecip_pivot(float2 a) {
 }
 __device__ inline double2 crecip_pivot(double2 a) { return crecip(a); }
 
-// LDS of the panel kernel (candidates double-buffered by column parity)
-template <typename T, int NT, int W> struct PanelShared {
+// Single-precision pivot search on 64-bit keys: (bits of |re|+|im|) << 32 |
+// ~row.  For non-negative floats the bit pattern orders like the value, and
+// ~row makes the smaller row win a tie, so the largest key is LAPACK's pivot.
+// Rows outside [j, n) and NaN magnitudes carry key 0 and never win; a zero
+// magnitude has a nonzero key.  One 64-bit compare per reduction step.
+__device__ inline uint64_t pivot_key(float m, int row, bool valid) {
+    return (valid && m == m) ? (uint64_t(__float_as_uint(m)) << 32) | uint32_t(~row) : uint64_t(0);
+}
+template <int CTRL, int ROWS> __device__ inline uint64_t dpp_key(uint64_t v) {
+    int lo, hi;
+    if constexpr (ROWS == 0xF) {   // every lane written: no old value needed
+        lo = __builtin_amdgcn_mov_dpp(int(v), CTRL, 0xF, 0xF, false);
+        hi = __builtin_amdgcn_mov_dpp(int(v >> 32), CTRL, 0xF, 0xF, false);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(int(v), int(v), CTRL, ROWS, 0xF, false);
+        hi = __builtin_amdgcn_update_dpp(int(v >> 32), int(v >> 32), CTRL, ROWS, 0xF, false);
+    }
+    return (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo);
+}
+template <int CTRL, int ROWS> __device__ inline void key_step(uint64_t& k) {
+    const uint64_t o = dpp_key<CTRL, ROWS>(k);
+    k = o > k ? o : k;
+}
+__device__ inline void row16_key_max(uint64_t& k) {
+    key_step<0xB1, 0xF>(k);
+    key_step<0x4E, 0xF>(k);
+    key_step<0x124, 0xF>(k);
+    key_step<0x128, 0xF>(k);
+}
+__device__ inline uint64_t readlane_key(uint64_t k, int l) {
+    const int lo = __builtin_amdgcn_readlane(int(k), l), hi = __builtin_amdgcn_readlane(int(k >> 32), l);
+    return (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo);
+}
+__device__ inline uint64_t wave_key_max(uint64_t k) {
+    row16_key_max(k);
+    key_step<0x142, 0xA>(k);   // row_bcast:15
+    key_step<0x143, 0xC>(k);   // row_bcast:31
+    return readlane_key(k, 63);
+}
+
+// LDS of the panel kernel (candidates double-buffered by column parity);
+// the row buffers come first so their 16-byte vectors stay aligned
+template <typename T, int NT, int W> struct alignas(16) PanelShared {
     using V = typename C2<T>::t;
     static constexpr int NW = NT / 64;
+    V cand_row[2][NW][W];
+    V stage[NBMAX - W][2 * W];
+    V Ls[W][W];
+    uint64_t cand_k[2][NW];
     T cand_v[2][NW];
     int cand_i[2][NW];
-    V cand_row[2][NW][W];
-    V jrow[2][W];
-    V Ls[W][W];
     int piv_s[W];
     int cand_s[2 * W], src_s[2 * W];
-    V stage[NBMAX - W][2 * W];
 };
 
+// Columns [c_from, W) of a row held in LDS, read as 16-byte vectors
+// (c_from is rounded down to a vector boundary).
+template <int W, int C_FROM> __device__ inline void lds_row(const float2* src, float2 (&dst)[W]) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int c2 = C_FROM / 2; c2 < W / 2; ++c2) {
+        const float4 q = s4[c2];
+        dst[2 * c2] = float2{q.x, q.y};
+        dst[2 * c2 + 1] = float2{q.z, q.w};
+    }
+}
+template <int W, int C_FROM> __device__ inline void lds_row(const double2* src, double2 (&dst)[W]) {
+#pragma unroll
+    for (int c = C_FROM; c < W; ++c) dst[c] = src[c];
+}
+
 // Column JJ of the panel (then JJ+1, ...): a compile-time recursion, so the
-// register-resident panel is only ever indexed by constants.
+// register-resident panel is only ever indexed by constants.  Row exchanges
+// are virtual: lrow[r] is the row that register row r currently holds, an
+// exchange of rows j and p swaps two of these labels, and the write-back puts
+// every register row at its label.
 template <typename T, int NT, int RPT, int W, int JJ>
-__device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], PanelShared<T, NT, W>& sh,
-                                              const PanelArgs& pa, int b, int tid) {
+__device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], int (&lrow)[RPT],
+                                              PanelShared<T, NT, W>& sh, const PanelArgs& pa, int b, int tid) {
     if constexpr (JJ < W) {
         using V = typename C2<T>::t;
         constexpr int NW = NT / 64;
         constexpr int par = JJ & 1;
-        const int j0 = pa.j0, n = pa.n;
+        const int n = pa.n;
         if (JJ >= pa.w) return;
         const int lane = tid & 63, wave = tid >> 6;
-        const int j = j0 + JJ;
-        // local candidate: rows outside [j, n) carry -2 and never win; a NaN
-        // never wins a comparison; bidx stays j when no row qualifies
+        const int j = pa.j0 + JJ;
+        // wave candidate: the label of its row (-1: the wave has none)
+        int bidx = -1;
         T best = T(-1);
-        int bidx = j;
+        uint64_t wkey = 0;
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            const T m = fabs(a[r][JJ].x) + fabs(a[r][JJ].y);
-            take_if_better((row >= j && row < n) ? m : T(-2), row, best, bidx);
+            for (int r = 0; r < RPT; ++r) {
+                const uint64_t k =
+                    pivot_key(fabsf(a[r][JJ].x) + fabsf(a[r][JJ].y), lrow[r], lrow[r] >= j && lrow[r] < n);
+                wkey = k > wkey ? k : wkey;
+            }
+            wkey = wave_key_max(wkey);
+            if (wkey != 0) bidx = int(~uint32_t(wkey));
+        } else {
+            // rows outside [j, n) carry -2 and never win; a NaN never wins a comparison
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const T m = fabs(a[r][JJ].x) + fabs(a[r][JJ].y);
+                take_if_better((lrow[r] >= j && lrow[r] < n) ? m : T(-2), lrow[r], best, bidx);
+            }
+            wave_argmax(best, bidx);
+            if (!(best >= T(0))) bidx = -1;   // no qualifying row in this wave
         }
-        wave_argmax(best, bidx);
-        // the owner of the wave's best row publishes it; the owner of row j publishes row j
+        // the holder of the wave's candidate publishes that row
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            if (row == bidx) {
+            if (lrow[r] == bidx) {
 #pragma unroll
                 for (int c = 0; c < W; ++c) sh.cand_row[par][wave][c] = a[r][c];
             }
-            if (row == j) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) sh.jrow[par][c] = a[r][c];
-            }
         }
         if (lane == 0) {
-            sh.cand_v[par][wave] = best;
-            sh.cand_i[par][wave] = bidx;
+            if constexpr (sizeof(T) == 4) {
+                sh.cand_k[par][wave] = wkey;
+            } else {
+                sh.cand_v[par][wave] = bidx >= 0 ? best : T(-1);
+                sh.cand_i[par][wave] = bidx >= 0 ? bidx : INT_MAX;
+            }
         }
         __syncthreads();
         // every wave reduces the NW candidates at once (lane q holds wave q's);
-        // the winner was published by the wave that owns its row
-        best = T(-1);
-        bidx = INT_MAX;
-        if (lane < NW) {
-            best = sh.cand_v[par][lane];
-            bidx = sh.cand_i[par][lane];
+        // wb is the wave that published the winner.  No qualifying row at
+        // all (a NaN column) is handled like a zero pivot on row j itself.
+        int p, wb;
+        bool zero;
+        if constexpr (sizeof(T) == 4) {
+            const uint64_t mine = lane < NW ? sh.cand_k[par][lane] : uint64_t(0);
+            uint64_t k = mine;
+            row16_key_max(k);
+            k = readlane_key(k, 0);
+            const uint64_t hit = __ballot(lane < NW && mine == k);
+            wb = k != 0 ? __ffsll(static_cast<long long>(hit)) - 1 : -1;
+            p = k != 0 ? int(~uint32_t(k)) : j;
+            zero = (k >> 32) == 0;
+        } else {
+            T bv = T(-1);
+            int bi = INT_MAX;
+            if (lane < NW) {
+                bv = sh.cand_v[par][lane];
+                bi = sh.cand_i[par][lane];
+            }
+            const int mine = bi;
+            row16_argmax(bv, bi);
+            bv = readlane_v(bv, 0);
+            bi = __builtin_amdgcn_readlane(bi, 0);
+            const uint64_t hit = __ballot(lane < NW && mine == bi);
+            wb = bv >= T(0) ? __ffsll(static_cast<long long>(hit)) - 1 : -1;
+            zero = !(bv > T(0));
+            p = bv >= T(0) ? bi : j;
         }
-        row16_argmax(best, bidx);
-        best = readlane_v(best, 0);
-        const int p = __builtin_amdgcn_readlane(bidx, 0);
-        const int wb = ((p - j0) % NT) >> 6;
         if (tid == 0) {
             sh.piv_s[JJ] = p;
             pa.ipiv[size_t(b) * n + j] = p;
-            if (best == T(0)) atomicCAS(pa.info + b, 0, j + 1);
+            if (zero) atomicCAS(pa.info + b, 0, j + 1);
         }
-        // a zero pivot leaves the column as it is (its entries below are zero)
-        const V inv = best != T(0) ? crecip_pivot(sh.cand_row[par][wb][JJ]) : V{T(0), T(0)};
+        // exchange the labels of rows j and p
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) lrow[r] = lrow[r] == j ? p : (lrow[r] == p ? j : lrow[r]);
+        // pivot row (no qualifying row: the zero pivot skips the update, and
+        // inv = 0 keeps every multiplier and update zero)
+        V prow[W];
+        if (wb >= 0) {
+            lds_row<W, JJ>(&sh.cand_row[par][wb][0], prow);
+        } else {
+#pragma unroll
+            for (int c = 0; c < W; ++c) prow[c] = V{T(0), T(0)};
+        }
+        const V inv = !zero ? crecip_pivot(prow[JJ]) : V{T(0), T(0)};
         V l[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const int row = j0 + tid + r * NT;
-            if (p != j && row == j) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) a[r][c] = sh.cand_row[par][wb][c];
-            } else if (p != j && row == p) {
-#pragma unroll
-                for (int c = 0; c < W; ++c) a[r][c] = sh.jrow[par][c];
-            }
             // multipliers below the diagonal; zero above it (no update there)
-            l[r] = row > j ? cm(a[r][JJ], inv) : V{T(0), T(0)};
-            if (row > j) a[r][JJ] = l[r];
+            const bool below = lrow[r] > j;
+            l[r] = below ? cm(a[r][JJ], inv) : V{T(0), T(0)};
+            if (below) a[r][JJ] = l[r];
         }
-        // rank-1 update, one pivot-row entry at a time (columns past w are zero)
+        // rank-1 update (columns past w are zero)
 #pragma unroll
         for (int c = JJ + 1; c < W; ++c) {
-            const V u = sh.cand_row[par][wb][c];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) a[r][c] = cfms(a[r][c], l[r], u);
+            for (int r = 0; r < RPT; ++r) a[r][c] = cfms(a[r][c], l[r], prow[c]);
         }
-        panel_columns<T, NT, RPT, W, JJ + 1>(a, sh, pa, b, tid);
+        panel_columns<T, NT, RPT, W, JJ + 1>(a, lrow, sh, pa, b, tid);
     }
 }
 
 // One workgroup per matrix factors rows [j0, n) x columns [j0, j0+w) held in
-// registers (thread t owns rows j0 + t + r NT).  One barrier per column: each
-// wave publishes its best candidate together with that row, and the owner of
-// row j publishes row j; after the barrier every thread picks the winner,
-// the two owners exchange rows, and all threads scale and update.
+// registers (thread t starts with rows j0 + t + r NT).  One barrier per
+// column: each wave publishes its best candidate together with that row;
+// after the barrier every thread picks the winner, the labels of rows j and
+// p are exchanged (no data moves), and all threads scale and update.
 template <typename T, int NT, int RPT, int W>
 __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     using V = typename C2<T>::t;
@@ -281,21 +373,25 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
             a[r][c] = (row < n && c < w) ? A[size_t(j0 + c) * lda + row] : V{T(0), T(0)};
     }
 
-    panel_columns<T, NT, RPT, W, 0>(a, sh, pa, b, tid);
+    int lrow[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) lrow[r] = j0 + tid + r * NT;
+    panel_columns<T, NT, RPT, W, 0>(a, lrow, sh, pa, b, tid);
     __syncthreads();
 
-    // write the panel back; keep its unit-lower top block in LDS
+    // write every register row back at its label; keep the unit-lower top
+    // block in LDS
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int row = j0 + tid + r * NT;
+        const int row = lrow[r];
         if (row < n) {
 #pragma unroll
             for (int c = 0; c < W; ++c)
                 if (c < w) A[size_t(j0 + c) * lda + row] = a[r][c];
         }
-        if (r == 0 && tid < w) {
+        if (row >= j0 && row < j0 + w) {
 #pragma unroll
-            for (int c = 0; c < W; ++c) Ls[tid][c] = a[0][c];
+            for (int c = 0; c < W; ++c) Ls[row - j0][c] = a[r][c];
         }
     }
     // rows touched by this panel's exchanges: the w top rows and the w pivot
