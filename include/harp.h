@@ -167,9 +167,11 @@ harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t
  * row i at step i.  The rows are grouped in solve groups of 256: the row
  * exchanges of a group are applied to the multipliers of that group but not to
  * those of earlier groups (the forward solve applies them group by group).
- * d_aux (device, reduced_factor_ws bytes, caller-owned) receives the inverses
- * of the diagonal 256 x 256 blocks of L and U and each group's row
- * permutation; pass it unchanged to reduced_solve.  d_info[b] = 0, or i + 1 if
+ * d_aux (device, reduced_factor_ws bytes, caller-owned) serves as scratch
+ * during the elimination (each 64-column block's inverse unit-lower diagonal
+ * block and row-exchange map) and on return holds the inverses of the
+ * diagonal 256 x 256 blocks of L and U and each group's row permutation;
+ * pass it unchanged to reduced_solve.  d_info[b] = 0, or i + 1 if
  * U(i, i) is exactly zero (the factorisation then continues; a solve with it
  * is meaningless).  Asynchronous. */
 harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void *d_A, int64_t lda,

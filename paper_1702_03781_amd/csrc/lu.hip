@@ -16,7 +16,11 @@
 //                        columns of the outer block; unit-lower solve of the
 //                        outer block's columns to the right of the panel
 //       cgemm          : update of the rest of the outer block (MFMA)
-//     laswp_trsm_kernel: row exchanges + unit-lower solve of the block row U12
+//     (the last panel also writes the inverse of the block's unit-lower
+//      diagonal block L11 and the block's row-exchange map to a scratch)
+//     laswp_kernel     : the block's row exchanges applied to the trailing
+//                        columns (and to earlier columns of the solve group)
+//     cgemm            : block row U12 = L11^-1 A12, in place (MFMA)
 //     cgemm            : trailing update A22 -= L21 U12 (MFMA, the hot loop)
 // Row exchanges of a later outer block are not applied to the multipliers of
 // earlier blocks; the forward solve applies the exchanges block by block in
@@ -69,10 +73,21 @@ struct PanelArgs {
     int n, k0, kend, j0, w;
     int32_t* ipiv;      // [batch][n]
     int32_t* info;      // [batch]
+    void* blk;          // last panel of an outer block: per-matrix block scratch, else null
 };
 
 // widest outer block the panel kernel serves (its LDS staging is sized for it)
 constexpr int NBMAX = 64;
+
+// Per-matrix scratch of one outer block, written by its last panel and read
+// by the block-row solve: the inverse of the unit-lower diagonal block
+// (NBMAX x NBMAX complex, column-major, identity past the block's width) and
+// the block's row-exchange map (cand[2 NBMAX]: rows touched; src[2 NBMAX]:
+// where each one's content comes from after all the block's exchanges).
+template <typename T> struct BlkScratch {
+    static constexpr int64_t linv_bytes = int64_t(NBMAX) * NBMAX * 2 * int64_t(sizeof(T));
+    static constexpr int64_t stride = ((linv_bytes + 4 * NBMAX * 4) + 255) / 256 * 256;
+};
 
 // Wave-wide argmax of (value, row) with the LAPACK tie rule (larger value,
 // then smaller row).  DPP moves inside each 16-lane row (quad swaps, then
@@ -341,6 +356,111 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
     }
 }
 
+// LDS of the block inverse: M holds L (strictly lower part, M[i][j], i > j)
+// and L^-1 transposed (strictly upper part: M[j][i] = L^-1(i, j), i > j) --
+// both unit-lower, so one square array holds them -- plus a product buffer.
+template <typename T> struct BlkShared {
+    using V = typename C2<T>::t;
+    V M[NBMAX][NBMAX + 1];
+    V tmp[NBMAX / 2][NBMAX / 2 + 1];
+    int pv[NBMAX];
+};
+
+template <typename V> __device__ inline V cfma(V acc, V a, V b) {   // acc + a * b
+    acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+    acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+    return acc;
+}
+
+// One level of the blocked inversion: for each of the NBMAX / (2h) diagonal
+// blocks of size 2h with inverted h x h diagonal halves A^-1, B^-1 and
+// off-diagonal part C of L, the off-diagonal part of the inverse is
+// -B^-1 (C A^-1).
+template <typename T, int NT, int H>
+__device__ inline void linv_level(BlkShared<T>& bs, int tid) {
+    using V = typename C2<T>::t;
+    constexpr int NBLK = NBMAX / (2 * H);
+    static_assert(NBLK * H <= NBMAX / 2, "product buffer");
+    // T = C A^-1 : T(i, j) = C(i, j) + sum_{k > j} C(i, k) A^-1(k, j)
+    for (int e = tid; e < NBLK * H * H; e += NT) {
+        const int blk = e / (H * H), i = (e / H) % H, j = e % H, o = 2 * H * blk;
+        V acc = bs.M[o + H + i][o + j];
+        for (int k = j + 1; k < H; ++k) acc = cfma(acc, bs.M[o + H + i][o + k], bs.M[o + j][o + k]);
+        bs.tmp[blk * H + i][j] = acc;
+    }
+    __syncthreads();
+    // R = -B^-1 T : R(i, j) = -(T(i, j) + sum_{k < i} B^-1(i, k) T(k, j)), stored transposed
+    for (int e = tid; e < NBLK * H * H; e += NT) {
+        const int blk = e / (H * H), i = (e / H) % H, j = e % H, o = 2 * H * blk;
+        V acc = bs.tmp[blk * H + i][j];
+        for (int k = 0; k < i; ++k) acc = cfma(acc, bs.M[o + H + k][o + H + i], bs.tmp[blk * H + k][j]);
+        bs.M[o + j][o + H + i] = V{-acc.x, -acc.y};
+    }
+    __syncthreads();
+}
+
+// Last panel of an outer block [k0, kend): with the block's unit-lower
+// diagonal block now final in A, write its inverse and the block's row
+// exchange map to the block scratch.  The inverse is blocked: 16 x 16
+// diagonal blocks by substitution (one thread per column), then two doubling
+// levels of products.
+template <typename T, int NT>
+__device__ void block_finish(const PanelArgs& pa, int b, int tid, BlkShared<T>& bs) {
+    using V = typename C2<T>::t;
+    static_assert(NT >= 64, "one thread per column of the 16 x 16 diagonal blocks");
+    __syncthreads();   // this workgroup's writes of the panel and its exchanges are visible
+    const V* A = reinterpret_cast<const V*>(pa.A) + size_t(b) * pa.sA;
+    const int k0 = pa.k0, nbo = pa.kend - pa.k0, n = pa.n;
+    char* base = reinterpret_cast<char*>(pa.blk) + size_t(b) * BlkScratch<T>::stride;
+    V* G = reinterpret_cast<V*>(base);
+    int32_t* map = reinterpret_cast<int32_t*>(base + BlkScratch<T>::linv_bytes);
+    for (int e = tid; e < nbo; e += NT) bs.pv[e] = pa.ipiv[size_t(b) * n + k0 + e];
+    for (int e = tid; e < NBMAX * NBMAX; e += NT) {
+        const int i = e % NBMAX, j = e / NBMAX;
+        bs.M[i][j] = (i > j && i < nbo) ? A[size_t(k0 + j) * pa.lda + k0 + i] : V{T(0), T(0)};
+    }
+    __syncthreads();
+    // exchange map: rows touched (the block's rows and its pivot rows) and the
+    // source of each after all exchanges, by walking the exchanges backwards
+    if (tid < 2 * nbo) {
+        const int r = tid < nbo ? k0 + tid : bs.pv[tid - nbo];
+        int src = r;
+        for (int q = nbo - 1; q >= 0; --q) {
+            if (src == k0 + q) src = bs.pv[q];
+            else if (src == bs.pv[q]) src = k0 + q;
+        }
+        map[tid] = r;
+        map[2 * NBMAX + tid] = src;
+    }
+    // 16 x 16 diagonal blocks: thread (d, c) forms column c of block d's inverse
+    if (tid < 64) {
+        const int o = 16 * (tid >> 4), c = tid & 15;
+        V x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (i <= c) {
+                x[i] = V{i == c ? T(1) : T(0), T(0)};
+                continue;
+            }
+            V acc = bs.M[o + i][o + c];
+#pragma unroll
+            for (int k = 0; k < i; ++k)
+                if (k > c) acc = cfma(acc, bs.M[o + i][o + k], x[k]);
+            x[i] = V{-acc.x, -acc.y};
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i > c) bs.M[o + c][o + i] = x[i];
+    }
+    __syncthreads();
+    linv_level<T, NT, 16>(bs, tid);
+    linv_level<T, NT, 32>(bs, tid);
+    for (int e = tid; e < NBMAX * NBMAX; e += NT) {
+        const int i = e % NBMAX, j = e / NBMAX;
+        G[e] = i > j ? bs.M[j][i] : V{i == j ? T(1) : T(0), T(0)};
+    }
+}
+
 // One workgroup per matrix factors rows [j0, n) x columns [j0, j0+w) held in
 // registers (thread t starts with rows j0 + t + r NT).  One barrier per
 // column: each wave publishes its best candidate together with that row;
@@ -445,187 +565,63 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
             for (int i = q + 1; i < W; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
         }
     }
+    if (pa.blk) {
+        __shared__ BlkShared<T> bs;
+        block_finish<T, NT>(pa, b, tid, bs);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// row exchanges + unit-lower solve of a block row (trailing columns of the
-// factorisation, or the right-hand sides in the forward solve)
+// row exchanges of an outer block applied to other columns, from the exchange
+// map its last panel wrote: the 2 nbo rows the exchanges touch are gathered
+// (from their sources) and scattered back.  The block row is then solved by
+// a matrix-core product with the block's inverse unit-lower diagonal block.
 // ---------------------------------------------------------------------------
 
-struct TrsmArgs {
-    const void* LU;
-    int64_t lda, sL;
-    const int32_t* ipiv;   // [batch][n]
-    int n, k0, nbo;
+struct LaswpArgs {
+    const void* blk;       // block scratch, BlkScratch<T>::stride bytes per matrix
+    int nbo;               // width of the outer block
     void* X;
     int64_t ldx, sX;
-    int c_begin, c_end;    // columns of X to exchange and solve
-    const int32_t* active;
-    int l_begin = 0, l_end = 0;  // columns of X that only take the row exchanges
+    int c_begin, c_end;    // columns [c_begin, c_end) ...
+    int l_begin, l_end;    // ... and [l_begin, l_end) take the exchanges
 };
 
-// Block-row solves on CB columns per 256-thread workgroup.  The block row
-// (and, for the lower solve, the rows its exchanges displace) is gathered into
-// LDS, solved there in 16-row chunks (a chunk's diagonal solve by one thread
-// per column, the update of the later chunks by all threads), and written
-// back with coalesced stores.
-constexpr int kCh = 16;
+template <typename T> struct LaswpCols { static constexpr int CB = 64 * 8 / int(2 * sizeof(T)); };
 
-template <typename T> struct TrsmCols;
-template <> struct TrsmCols<float> { static constexpr int CB = 64; };
-template <> struct TrsmCols<double> { static constexpr int CB = 32; };
-
-template <typename T, int NB>
-__global__ void __launch_bounds__(256) laswp_trsm_lower_kernel(TrsmArgs ta) {
+template <typename T>
+__global__ void __launch_bounds__(256) laswp_kernel(LaswpArgs la) {
     using V = typename C2<T>::t;
-    constexpr int CB = TrsmCols<T>::CB;
-    static_assert(NB % kCh == 0, "block size");
+    constexpr int CB = LaswpCols<T>::CB;
     const int b = blockIdx.y;
-    if (ta.active && ta.active[b] == 0) return;
-    const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
-    V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
-    const int32_t* ipiv = ta.ipiv + size_t(b) * ta.n;
-    const int k0 = ta.k0, nbo = ta.nbo, tid = threadIdx.x;
-    // the first tiles take the exchange-only columns [l_begin, l_end)
-    const int left_tiles = (ta.l_end - ta.l_begin + CB - 1) / CB;
+    const int32_t* map = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(la.blk) +
+                                                          size_t(b) * BlkScratch<T>::stride +
+                                                          BlkScratch<T>::linv_bytes);
+    V* X = reinterpret_cast<V*>(la.X) + size_t(b) * la.sX;
+    const int nbo = la.nbo, tid = threadIdx.x, n2 = 2 * nbo;
+    // the first tiles take the columns [l_begin, l_end)
+    const int left_tiles = (la.l_end - la.l_begin + CB - 1) / CB;
     const bool left = int(blockIdx.x) < left_tiles;
-    const int c0 = left ? ta.l_begin + blockIdx.x * CB : ta.c_begin + (blockIdx.x - left_tiles) * CB;
-    const int ncols = min(CB, (left ? ta.l_end : ta.c_end) - c0);
-    __shared__ V Ls[NB][NB + 1];
-    __shared__ V S[CB][2 * NB + 1];
-    __shared__ int pv[NB], cand[2 * NB], src[2 * NB];
-    if (!left) {
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int i = e % NB, j = e / NB;
-            Ls[i][j] = (i < nbo && j < nbo && i > j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
-        }
-    }
-    for (int e = tid; e < nbo; e += 256) pv[e] = ipiv[k0 + e];
-    __syncthreads();
-    const int n2 = 2 * nbo;
+    const int c0 = left ? la.l_begin + blockIdx.x * CB : la.c_begin + (blockIdx.x - left_tiles) * CB;
+    const int ncols = min(CB, (left ? la.l_end : la.c_end) - c0);
+    __shared__ V S[CB][2 * NBMAX + 1];
+    __shared__ int cand[2 * NBMAX], src[2 * NBMAX];
     if (tid < n2) {
-        const int r = tid < nbo ? k0 + tid : pv[tid - nbo];
-        int sr = r;
-        for (int q = nbo - 1; q >= 0; --q) {
-            if (sr == k0 + q) sr = pv[q];
-            else if (sr == pv[q]) sr = k0 + q;
-        }
-        cand[tid] = r;
-        src[tid] = sr;
+        cand[tid] = map[tid];
+        src[tid] = map[2 * NBMAX + tid];
     }
     __syncthreads();
     for (int e = tid; e < n2 * ncols; e += 256) {
         const int t = e % n2, c = e / n2;
-        S[c][t] = X[size_t(c0 + c) * ta.ldx + src[t]];
+        S[c][t] = X[size_t(c0 + c) * la.ldx + src[t]];
     }
     __syncthreads();
-    if (left) {
-        for (int e = tid; e < n2 * ncols; e += 256) {
-            const int t = e % n2, c = e / n2;
-            const int r = cand[t];
-            if (t >= nbo && r < k0 + nbo) continue;   // written by its top-row entry
-            X[size_t(c0 + c) * ta.ldx + r] = S[c][t];
-        }
-        return;
-    }
-    // rows displaced below the block row
-    for (int e = tid; e < nbo * ncols; e += 256) {
-        const int t = nbo + e % nbo, c = e / nbo;
+    const int top_end = cand[0] + nbo;   // cand[0] is the block's first row
+    for (int e = tid; e < n2 * ncols; e += 256) {
+        const int t = e % n2, c = e / n2;
         const int r = cand[t];
-        if (r >= k0 + nbo) X[size_t(c0 + c) * ta.ldx + r] = S[c][t];
-    }
-    // forward substitution with the unit-lower diagonal block
-    const int nch = (nbo + kCh - 1) / kCh;
-    for (int q = 0; q < nch; ++q) {
-        if (tid < ncols) {
-            V x[kCh];
-#pragma unroll
-            for (int i = 0; i < kCh; ++i) x[i] = S[tid][q * kCh + i];
-#pragma unroll
-            for (int i = 1; i < kCh; ++i)
-#pragma unroll
-                for (int j = 0; j < i; ++j) x[i] = cfms(x[i], Ls[q * kCh + i][q * kCh + j], x[j]);
-#pragma unroll
-            for (int i = 0; i < kCh; ++i) S[tid][q * kCh + i] = x[i];
-        }
-        __syncthreads();
-        const int rows_below = nbo - (q + 1) * kCh;
-        if (rows_below > 0) {
-            for (int e = tid; e < rows_below * ncols; e += 256) {
-                const int i = (q + 1) * kCh + e % rows_below, c = e / rows_below;
-                V acc = S[c][i];
-#pragma unroll
-                for (int j = 0; j < kCh; ++j) acc = cfms(acc, Ls[i][q * kCh + j], S[c][q * kCh + j]);
-                S[c][i] = acc;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < nbo * ncols; e += 256) {
-        const int i = e % nbo, c = e / nbo;
-        X[size_t(c0 + c) * ta.ldx + k0 + i] = S[c][i];
-    }
-}
-
-// upper solve with the non-unit diagonal block U11 (backward substitution)
-template <typename T, int NB>
-__global__ void __launch_bounds__(256) trsm_upper_kernel(TrsmArgs ta) {
-    using V = typename C2<T>::t;
-    constexpr int CB = TrsmCols<T>::CB;
-    static_assert(NB % kCh == 0, "block size");
-    const int b = blockIdx.y;
-    if (ta.active && ta.active[b] == 0) return;
-    const V* LU = reinterpret_cast<const V*>(ta.LU) + size_t(b) * ta.sL;
-    V* X = reinterpret_cast<V*>(ta.X) + size_t(b) * ta.sX;
-    const int k0 = ta.k0, nbo = ta.nbo, tid = threadIdx.x;
-    const int c0 = ta.c_begin + blockIdx.x * CB;
-    const int ncols = min(CB, ta.c_end - c0);
-    __shared__ V Us[NB][NB + 1];
-    __shared__ V S[CB][NB + 1];
-    __shared__ V dinv[NB];
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int i = e % NB, j = e / NB;
-        Us[i][j] = (i < nbo && j < nbo && i <= j) ? LU[size_t(k0 + j) * ta.lda + k0 + i] : V{T(0), T(0)};
-    }
-    for (int e = tid; e < nbo * ncols; e += 256) {
-        const int i = e % nbo, c = e / nbo;
-        S[c][i] = X[size_t(c0 + c) * ta.ldx + k0 + i];
-    }
-    __syncthreads();
-    for (int e = tid; e < NB; e += 256) dinv[e] = e < nbo ? crecip(Us[e][e]) : V{T(0), T(0)};
-    __syncthreads();
-    const int nch = (nbo + kCh - 1) / kCh;
-    for (int q = nch - 1; q >= 0; --q) {
-        const int hi = min(kCh, nbo - q * kCh);    // rows in this chunk
-        if (tid < ncols) {
-            V x[kCh];
-#pragma unroll
-            for (int i = 0; i < kCh; ++i) x[i] = i < hi ? S[tid][q * kCh + i] : V{T(0), T(0)};
-#pragma unroll
-            for (int i = kCh - 1; i >= 0; --i) {
-#pragma unroll
-                for (int j = i + 1; j < kCh; ++j) x[i] = cfms(x[i], Us[q * kCh + i][q * kCh + j], x[j]);
-                x[i] = i < hi ? cm(x[i], dinv[q * kCh + i]) : V{T(0), T(0)};
-            }
-#pragma unroll
-            for (int i = 0; i < kCh; ++i)
-                if (i < hi) S[tid][q * kCh + i] = x[i];
-        }
-        __syncthreads();
-        const int rows_above = q * kCh;
-        if (rows_above > 0) {
-            for (int e = tid; e < rows_above * ncols; e += 256) {
-                const int i = e % rows_above, c = e / rows_above;
-                V acc = S[c][i];
-                for (int j = 0; j < hi; ++j) acc = cfms(acc, Us[i][q * kCh + j], S[c][q * kCh + j]);
-                S[c][i] = acc;
-            }
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < nbo * ncols; e += 256) {
-        const int i = e % nbo, c = e / nbo;
-        X[size_t(c0 + c) * ta.ldx + k0 + i] = S[c][i];
+        if (t >= nbo && r < top_end) continue;   // written by its top-row entry
+        X[size_t(c0 + c) * la.ldx + r] = S[c][t];
     }
 }
 
@@ -872,12 +868,15 @@ harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
     return HARP_E_ARG;
 }
 
-// 1024 threads (16 waves) hide the per-column latency best; rows per thread
-// grow with the panel height
+// Two rows per thread while the panel is at most 2048 rows high (the
+// workgroup shrinks with the panel: fewer waves share the per-column
+// reductions), then more rows per thread with 1024 threads.
 template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
     if (pa.w > W) return HARP_E_ARG;
+    if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
+    if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
     if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, W>(pa, batch, st);
     if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, W>(pa, batch, st);
     if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, W>(pa, batch, st);
@@ -921,9 +920,10 @@ GemmArgs<T> sub_gemm(T* base, int64_t ld, int64_t s, int M, int N, int K, int ar
 }
 
 template <typename T>
-harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t* ipiv, int32_t* info,
+harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t* ipiv, int32_t* info, void* blk,
                         hipStream_t st) {
     constexpr int NB = LuCfg<T>::NB;
+    static_assert(NB <= NBMAX, "outer block");
     const int W = panel_width<T>(n);
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch));
@@ -931,9 +931,15 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
     harp_status s;
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
+        // row exchanges reach the block row to the right (then the unit-lower
+        // solve and the trailing update) and the earlier columns of the same
+        // solve group (so each group's multipliers share one row order)
+        const int lbeg = (k0 / kSB) * kSB;
+        const bool block_row = kend < n || lbeg < k0;
         for (int j0 = k0; j0 < kend; j0 += W) {
             const int w = std::min(W, kend - j0);
-            PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info};
+            const bool last = j0 + w == kend;
+            PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info, (last && block_row) ? blk : nullptr};
             if ((s = launch_getf2<T>(pa, W, batch, st)) != HARP_OK) return s;
             if (j0 + w < kend) {
                 GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - j0 - w, kend - j0 - w, w, j0 + w, j0, j0, j0 + w,
@@ -941,20 +947,38 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                 if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
             }
         }
-        // row exchanges reach the block row to the right (then the unit-lower
-        // solve and the trailing update) and the earlier columns of the same
-        // solve group (so each group's multipliers share one row order)
-        const int lbeg = (k0 / kSB) * kSB;
-        if (kend < n || lbeg < k0) {
-            TrsmArgs ta{A, lda, sA, ipiv, n, k0, nbo, A, lda, sA, kend, n, nullptr};
-            ta.l_begin = lbeg;
-            ta.l_end = k0;
-            constexpr int CB = TrsmCols<T>::CB;
+        if (block_row) {
+            LaswpArgs la{blk, nbo, A, lda, sA, kend, n, lbeg, k0};
+            constexpr int CB = LaswpCols<T>::CB;
             const int tiles = (n - kend + CB - 1) / CB + (k0 - lbeg + CB - 1) / CB;
             HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
-                             hipLaunchKernelGGL((laswp_trsm_lower_kernel<T, NB>), dim3(tiles, batch), dim3(256), 0,
-                                                st, ta));
+                             hipLaunchKernelGGL((laswp_kernel<T>), dim3(tiles, batch), dim3(256), 0, st, la));
             HARP_LAUNCH_CHECK();
+        }
+        if (kend < n) {
+            // block row U12 = L11^-1 (exchanged rows), in place: one row tile,
+            // so every workgroup reads its whole column block before writing it
+            GemmArgs<T> g{};
+            g.M = nbo;
+            g.N = n - kend;
+            g.K = nbo;
+            g.A = static_cast<const T*>(blk);
+            g.lda = NBMAX;
+            g.sA = BlkScratch<T>::stride / int64_t(2 * sizeof(T));
+            g.B = A + 2 * (size_t(kend) * lda + k0);
+            g.ldb = lda;
+            g.sB = sA;
+            g.C = nullptr;
+            g.ldc = lda;
+            g.sC = sA;
+            g.D = const_cast<T*>(g.B);
+            g.ldd = lda;
+            g.sD = sA;
+            g.alpha = T(1);
+            g.beta = T(0);
+            g.active = nullptr;
+            static_assert(NBMAX <= 64, "the in-place product needs a single row tile");
+            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
         }
         if (kend < n) {
             GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - kend, n - kend, nbo, kend, k0, k0, kend, kend, kend, T(-1),
@@ -1191,11 +1215,11 @@ extern "C" harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype
     harp_status s;
     if (dtype == HARP_C64) {
         float* A = static_cast<float*>(d_A);
-        if ((s = factor_impl<float>(n, batch, A, lda, stride_a, d_ipiv, d_info, stream)) != HARP_OK) return s;
+        if ((s = factor_impl<float>(n, batch, A, lda, stride_a, d_ipiv, d_info, d_aux, stream)) != HARP_OK) return s;
         return tri_inverse<float>(n, batch, A, lda, stride_a, d_ipiv, static_cast<float*>(d_aux), stream);
     }
     double* A = static_cast<double*>(d_A);
-    if ((s = factor_impl<double>(n, batch, A, lda, stride_a, d_ipiv, d_info, stream)) != HARP_OK) return s;
+    if ((s = factor_impl<double>(n, batch, A, lda, stride_a, d_ipiv, d_info, d_aux, stream)) != HARP_OK) return s;
     return tri_inverse<double>(n, batch, A, lda, stride_a, d_ipiv, static_cast<double*>(d_aux), stream);
 }
 
