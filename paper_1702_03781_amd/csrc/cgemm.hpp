@@ -274,13 +274,16 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN>
-inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream) {
+inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
+    const int cls = sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64;
     if (gemm_vec_ok(g))
-        hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, true>), grid, dim3(256), 0, stream, g);
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true>), grid,
+                             dim3(256), 0, g);
     else
-        hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, false>), grid, dim3(256), 0, stream, g);
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false>), grid,
+                             dim3(256), 0, g);
 }
 
 // Enqueue D = beta C + alpha A B for `batch` (x g.inner) matrices.  M, N, K
@@ -294,10 +297,15 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
     if (int64_t(batch) * g.inner > 65535) return HARP_E_ARG;
     // K == 0 runs the same kernel with an empty contraction: D = beta C
     const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
-    HARP_PROF_LAUNCH(sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64, stream,
-                     8.0 * double(g.M) * double(g.N) * double(g.K) * nb, 0.0,
-                     (g.N <= 32 ? launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream)
-                                : launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream)));
+    // algorithmic bytes: A and B read once, C read when beta != 0, D written
+    const bool reads_c = g.beta != T(0) && g.C != nullptr;
+    const double bytes = 2.0 * sizeof(T) * nb *
+                         (double(g.M) * g.K + double(g.K) * g.N + double(g.M) * g.N * (reads_c ? 2.0 : 1.0));
+    const double flops = 8.0 * double(g.M) * double(g.N) * double(g.K) * nb;
+    if (g.N <= 32)
+        launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
+    else
+        launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream, flops, bytes);
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }

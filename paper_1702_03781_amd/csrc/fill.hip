@@ -217,11 +217,11 @@ harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
     switch (a.Q) {
 #define HARP_FILL_CASE(QQ)                                                                 \
     case QQ:                                                                               \
-        HARP_PROF_LAUNCH(HARP_K_FILL, stream, 0.0,                                         \
-                         double(a.n_freq) * double(a.n_ant) * a.n_mbf * double(a.n_ant) * \
-                             a.n_mbf * (DUAL ? 24.0 : double(2 * sizeof(R))),              \
-                         hipLaunchKernelGGL((fill_kernel<R, QQ, DUAL>), grid, dim3(256), 0,\
-                                            stream, a, a.models, a.x, a.y, a.Z, a.Z32));   \
+        HARP_PROF_EXT_LAUNCH(HARP_K_FILL, stream, 0.0,                                     \
+                             double(a.n_freq) * double(a.n_ant) * a.n_mbf * double(a.n_ant) * \
+                                 a.n_mbf * (DUAL ? 24.0 : double(2 * sizeof(R))),          \
+                             (fill_kernel<R, QQ, DUAL>), grid, dim3(256), 0, a, a.models,  \
+                             a.x, a.y, a.Z, a.Z32);                                        \
         break;
         HARP_FILL_CASE(2)
         HARP_FILL_CASE(3)

@@ -860,8 +860,8 @@ template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
 template <typename T, int NT, int RPT, int W>
 harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
     if constexpr (panel_fits_r<T, NT, RPT, W>()) {
-        HARP_PROF_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0,
-                         hipLaunchKernelGGL((getf2_kernel<T, NT, RPT, W>), dim3(batch), dim3(NT), 0, st, pa));
+        HARP_PROF_EXT_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0, (getf2_kernel<T, NT, RPT, W>), dim3(batch), dim3(NT), 0,
+                             pa);
         HARP_LAUNCH_CHECK();
         return HARP_OK;
     }
@@ -951,8 +951,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
             LaswpArgs la{blk, nbo, A, lda, sA, kend, n, lbeg, k0};
             constexpr int CB = LaswpCols<T>::CB;
             const int tiles = (n - kend + CB - 1) / CB + (k0 - lbeg + CB - 1) / CB;
-            HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
-                             hipLaunchKernelGGL((laswp_kernel<T>), dim3(tiles, batch), dim3(256), 0, st, la));
+            HARP_PROF_EXT_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0, (laswp_kernel<T>), dim3(tiles, batch), dim3(256), 0,
+                                 la);
             HARP_LAUNCH_CHECK();
         }
         if (kend < n) {

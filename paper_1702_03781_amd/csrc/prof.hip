@@ -48,6 +48,23 @@ void end(int token, hipStream_t stream, double flops, double bytes) {
     r.bytes = bytes;
 }
 
+int begin_ext(int cls, hipEvent_t* start, hipEvent_t* stop) {
+    *start = *stop = nullptr;
+    if (!g_on) return -1;
+    Rec r{cls, next_event(), next_event(), 0.0, 0.0};
+    if (!r.start || !r.stop) return -1;
+    *start = r.start;
+    *stop = r.stop;
+    g_recs.push_back(r);
+    return int(g_recs.size()) - 1;
+}
+
+void end_ext(int token, double flops, double bytes) {
+    if (token < 0 || size_t(token) >= g_recs.size()) return;
+    g_recs[size_t(token)].flops = flops;
+    g_recs[size_t(token)].bytes = bytes;
+}
+
 }  // namespace prof
 }  // namespace harp
 
