@@ -235,6 +235,70 @@ harp_status embedded_patterns(const void *d_model, int32_t n_mbf, const double *
                               int32_t n_dir, void *d_E, void *d_ws, size_t ws_bytes,
                               hipStream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Adjoint with respect to the antenna positions (array synthesis)          */
+/* ------------------------------------------------------------------------ */
+/* Convention: a cotangent G of a complex output Z is the array with
+ * dJ = Re sum conj(G) dZ for a real objective J (PyTorch's complex autograd
+ * convention).  Position gradients are float64 [n_ant] and are accumulated
+ * (+=) into the caller's arrays.  The solve's adjoint reuses the factors of
+ * reduced_factor: Z is complex-symmetric (reciprocity), so Z^-H G =
+ * conj(Z^-1 conj(G)). */
+
+/* D = beta C + alpha A B for `batch` column-major complex matrices (complex64
+ * or complex128, interleaved; alpha, beta real; D may alias C; C may be null
+ * when beta = 0), on the matrix cores.  Strides in complex elements.
+ * Asynchronous. */
+harp_status harp_cgemm(harp_dtype dtype, int32_t M, int32_t N, int32_t K, int32_t batch, double alpha,
+                       const void *d_A, int64_t lda, int64_t stride_a, const void *d_B, int64_t ldb,
+                       int64_t stride_b, double beta, const void *d_C, int64_t ldc, int64_t stride_c,
+                       void *d_D, int64_t ldd, int64_t stride_d, hipStream_t stream);
+
+/* dst = op(src) for `batch` complex128 matrices of rows x cols (column-major,
+ * leading dimensions lds / ldd, batch strides in elements): op transposes
+ * when `transpose` != 0 (dst is then cols x rows) and conjugates when `conj`
+ * != 0.  In place only without transposition.  Asynchronous. */
+harp_status harp_cmatrix_copy(int32_t rows, int32_t cols, int32_t batch, const void *d_src, int64_t lds,
+                              int64_t stride_src, void *d_dst, int64_t ldd, int64_t stride_dst,
+                              int32_t transpose, int32_t conj, hipStream_t stream);
+
+/* Cotangent of X through the port admittances Y = W^T X:
+ * gX[(i,T), q] = conj(w_T) gY[i, q] (complex128; overwrites gX). */
+harp_status harp_port_admittance_vjp(const void *d_models, int64_t model_stride, int32_t n_freq,
+                                     int32_t n_mbf, int32_t n_ant, const void *d_gY, int64_t ldy,
+                                     int64_t stride_y, void *d_gX, int64_t ldx, int64_t stride_x,
+                                     hipStream_t stream);
+
+/* Workspace bytes of harp_fill_vjp. */
+harp_status harp_fill_vjp_ws(int32_t n_ant, size_t *bytes);
+
+/* Eq. (4) differentiated with respect to the positions (Sections II-A/B: the
+ * modified coordinates t = r_min / r and alpha of every pair): for one model
+ * (one frequency), gx_i += Re sum_ab W_ab dZ_ab/dx_i and likewise for y, over
+ * the ordered pairs with r <= ri (ri <= 0: all); W (complex128, n x n, ld ldw)
+ * plays the role of conj of the cotangent of Z.  Q must equal the model's Q;
+ * d_info (int32, device) is set to -1 when the model does not match.
+ * Deterministic (fixed-order reductions).  Asynchronous. */
+harp_status harp_fill_vjp(const void *d_model, int32_t n_mbf, int32_t Q, const double *d_x,
+                          const double *d_y, int32_t n_ant, double ri, const void *d_W, int64_t ldw,
+                          double *d_gx, double *d_gy, int32_t *d_info, void *d_ws, size_t ws_bytes,
+                          hipStream_t stream);
+
+/* Workspace bytes of embedded_patterns_vjp. */
+harp_status embedded_patterns_vjp_ws(int32_t n_mbf, int32_t n_ant, int32_t n_dir, int32_t n_ports,
+                                     size_t *bytes);
+
+/* Eqs. (5)-(6) differentiated: for the cotangent gE of the patterns
+ * (complex128 [n_ports][n_dir][2], as produced by embedded_patterns), adds
+ * A^H gE to gX (complex128 n x n_ports, ld ldgx; A the pattern operator
+ * E = A X) and the explicit dependence of the array phase on the positions
+ * to gx, gy.  Asynchronous. */
+harp_status embedded_patterns_vjp(const void *d_model, int32_t n_mbf, const double *d_x, const double *d_y,
+                                  int32_t n_ant, const void *d_X, int64_t ldx, int32_t n_ports,
+                                  const double *d_theta, const double *d_phi, int32_t n_dir,
+                                  const void *d_gE, void *d_gX, int64_t ldgx, double *d_gx, double *d_gy,
+                                  void *d_ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,18 @@ SIGNATURES = {
     "embedded_patterns_ws": (c_i32, [c_i32, c_i32, c_i32, c_szp]),
     "embedded_patterns": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_i64, c_i32, c_vp, c_vp,
                                   c_i32, c_vp, c_vp, c_sz, c_vp]),
+    "harp_cgemm": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_vp, c_i64, c_i64, c_vp,
+                           c_i64, c_i64, c_dbl, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
+    "harp_cmatrix_copy": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_i32,
+                                  c_i32, c_vp]),
+    "harp_port_admittance_vjp": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp,
+                                         c_i64, c_i64, c_vp]),
+    "harp_fill_vjp_ws": (c_i32, [c_i32, c_szp]),
+    "harp_fill_vjp": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_vp, c_i32, c_dbl, c_vp, c_i64, c_vp, c_vp,
+                              c_vp, c_vp, c_sz, c_vp]),
+    "embedded_patterns_vjp_ws": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_szp]),
+    "embedded_patterns_vjp": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_i64, c_i32, c_vp, c_vp,
+                                      c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_sz, c_vp]),
 }
 
 

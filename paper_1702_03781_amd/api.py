@@ -349,6 +349,149 @@ def embedded_patterns(model: Model, x: torch.Tensor, y: torch.Tensor, X: torch.T
     return E
 
 
+# --------------------------------------------------------------------------
+# adjoint (array synthesis): vector-Jacobian products and an autograd Function
+# --------------------------------------------------------------------------
+
+def harp_cgemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha: float = 1.0,
+               beta: float = 0.0, D: torch.Tensor | None = None) -> torch.Tensor:
+    """D = beta C + alpha A B for batched column-major complex matrices (MFMA)."""
+    A3 = A if A.dim() == 3 else A.unsqueeze(0)
+    B3 = B if B.dim() == 3 else B.unsqueeze(0)
+    b, M, K = A3.shape
+    N = B3.shape[-1]
+    if D is None:
+        D = colmajor(b, M, N, A3.dtype, A3.device)
+    pa, lda, sa = _cm(A3, "A")
+    pb, ldb, sb = _cm(B3, "B")
+    pd, ldd, sd = _cm(D, "D")
+    pc, ldc, sc = _cm(C, "C") if C is not None else (0, ldd, sd)
+    check(lib().harp_cgemm(_DT[A3.dtype], M, N, K, b, float(alpha), pa, lda, sa, pb, ldb, sb, float(beta),
+                           pc, ldc, sc, pd, ldd, sd, _stream(A3.device)), "harp_cgemm")
+    return D
+
+
+def cmatrix_copy(src: torch.Tensor, transpose: bool = False, conj: bool = False) -> torch.Tensor:
+    """op(src) for batched column-major complex128 matrices (transpose / conjugate)."""
+    S = src if src.dim() == 3 else src.unsqueeze(0)
+    b, r, c = S.shape
+    dst = colmajor(b, c, r, torch.complex128, S.device) if transpose else colmajor(b, r, c, torch.complex128,
+                                                                                     S.device)
+    ps, lds, ss = _cm(S, "src")
+    pd, ldd, sd = _cm(dst, "dst")
+    check(lib().harp_cmatrix_copy(r, c, b, ps, lds, ss, pd, ldd, sd, int(transpose), int(conj),
+                                  _stream(S.device)), "harp_cmatrix_copy")
+    return dst
+
+
+def harp_port_admittance_vjp(models: ModelBatch, gY: torch.Tensor) -> torch.Tensor:
+    """Cotangent of X through Y = W^T X: gX[(i,T), q] = conj(w_T) gY[i, q]."""
+    gY3 = gY if gY.dim() == 3 else gY.unsqueeze(0)
+    n_ant = gY3.shape[-1]
+    n = n_ant * models.n_mbf
+    gX = colmajor(models.n_freq, n, n_ant, torch.complex128, gY3.device)
+    py, ldy, sy = _cm(gY3, "gY")
+    px, ldx, sx = _cm(gX, "gX")
+    check(lib().harp_port_admittance_vjp(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
+                                         n_ant, py, ldy, sy, px, ldx, sx, _stream(gY3.device)),
+          "harp_port_admittance_vjp")
+    return gX
+
+
+def harp_fill_vjp(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, W: torch.Tensor, ri: float = 0.0,
+                  gx: torch.Tensor | None = None, gy: torch.Tensor | None = None):
+    """gx_i += Re sum_ab W_ab dZ_ab/dx_i (and y) for the first model of the batch."""
+    n_ant = int(x.numel())
+    dev = x.device
+    if gx is None:
+        gx = torch.zeros(n_ant, dtype=torch.float64, device=dev)
+    if gy is None:
+        gy = torch.zeros(n_ant, dtype=torch.float64, device=dev)
+    pw, ldw, _ = _cm(W, "W")
+    ws_b = ctypes.c_size_t()
+    check(lib().harp_fill_vjp_ws(n_ant, ctypes.byref(ws_b)), "harp_fill_vjp_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    x, y = x.contiguous(), y.contiguous()
+    check(lib().harp_fill_vjp(_ptr(models.data), models.n_mbf, models.Q, _ptr(x), _ptr(y), n_ant, float(ri),
+                              pw, ldw, _ptr(gx), _ptr(gy), _ptr(info), _ptr(ws), ws_b.value, _stream(dev)),
+          "harp_fill_vjp")
+    return gx, gy, info
+
+
+def embedded_patterns_vjp(model: Model, x: torch.Tensor, y: torch.Tensor, X: torch.Tensor,
+                          theta: torch.Tensor, phi: torch.Tensor, gE: torch.Tensor, gX: torch.Tensor,
+                          gx: torch.Tensor, gy: torch.Tensor):
+    """gX += A^H gE and gx, gy += the explicit position dependence of the patterns."""
+    X2 = X[0] if X.dim() == 3 else X
+    n_ant = int(x.numel())
+    n_ports = X2.shape[-1]
+    n_dir = int(theta.numel())
+    px, ldx, _ = _cm(X2, "X")
+    pg, ldg, _ = _cm(gX[0] if gX.dim() == 3 else gX, "gX")
+    gE = gE.contiguous()
+    ws_b = ctypes.c_size_t()
+    check(lib().embedded_patterns_vjp_ws(model.n_mbf, n_ant, n_dir, n_ports, ctypes.byref(ws_b)),
+          "embedded_patterns_vjp_ws")
+    ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=X2.device)
+    x, y = x.contiguous(), y.contiguous()
+    theta, phi = theta.contiguous(), phi.contiguous()
+    check(lib().embedded_patterns_vjp(_ptr(model.blob), model.n_mbf, _ptr(x), _ptr(y), n_ant, px, ldx,
+                                      n_ports, _ptr(theta), _ptr(phi), n_dir, _ptr(gE), pg, ldg, _ptr(gx),
+                                      _ptr(gy), _ptr(ws), ws_b.value, _stream(X2.device)),
+          "embedded_patterns_vjp")
+
+
+class ArrayResponse(torch.autograd.Function):
+    """(x, y) -> (Y, E): port admittances (n_ant x n_ant) and embedded element
+    patterns ([port][dir][theta/phi]) of one element type at one frequency,
+    through the Eq. 4 fill (complex128), a complex128 LU solve with one
+    right-hand side per port, and Eqs. 5-6.  The backward pass is the
+    hand-written adjoint: the patterns' and ports' vector-Jacobian products,
+    one adjoint solve with the same factors (Z is complex-symmetric), the
+    cotangent of Z as the product -conj(Lambda) X^T, and the fill's product."""
+
+    @staticmethod
+    def forward(ctx, x, y, model, theta, phi, ri):
+        mb = stack_models([model])
+        x64 = x.detach().to(torch.float64).contiguous()
+        y64 = y.detach().to(torch.float64).contiguous()
+        Z, _, info = harp_fill(mb, x64, y64, dtype="c128", ri=ri)
+        F = reduced_factor(Z)
+        B = harp_port_rhs(mb, int(x64.numel()))
+        X, _ = reduced_solve(F, B)
+        Y = harp_port_admittance(mb, X)
+        E = embedded_patterns(model, x64, y64, X, theta, phi)
+        ctx.save_for_backward(x64, y64, theta, phi)
+        ctx.F, ctx.X, ctx.mb, ctx.model, ctx.ri, ctx.info, ctx.finfo = F, X, mb, model, ri, info, F.info
+        return Y[0], E
+
+    @staticmethod
+    def backward(ctx, gY, gE):
+        x, y, theta, phi = ctx.saved_tensors
+        dev = x.device
+        n_ant = int(x.numel())
+        gx = torch.zeros(n_ant, dtype=torch.float64, device=dev)
+        gy = torch.zeros(n_ant, dtype=torch.float64, device=dev)
+        X = ctx.X
+        if gY is None:
+            gY = torch.zeros((n_ant, n_ant), dtype=torch.complex128, device=dev)
+        gX = harp_port_admittance_vjp(ctx.mb, gY.resolve_conj().transpose(0, 1).contiguous().transpose(0, 1))
+        if gE is not None:
+            embedded_patterns_vjp(ctx.model, x, y, X, theta, phi, gE.resolve_conj(), gX, gx, gy)
+        # Lambda = Z^-H gX = conj(Z^-1 conj(gX));  W = -conj(Lambda) X^T = -(Z^-1 conj(gX)) X^T
+        Lc, _ = reduced_solve(ctx.F, cmatrix_copy(gX, conj=True))
+        W = harp_cgemm(Lc, cmatrix_copy(X, transpose=True), alpha=-1.0)
+        harp_fill_vjp(ctx.mb, x, y, W, ri=ctx.ri, gx=gx, gy=gy)
+        return gx, gy, None, None, None, None
+
+
+def array_response(x: torch.Tensor, y: torch.Tensor, model: Model, theta: torch.Tensor, phi: torch.Tensor,
+                   ri: float = 0.0):
+    """Differentiable (Y, E) of a layout; see ArrayResponse."""
+    return ArrayResponse.apply(x, y, model, theta, phi, ri)
+
+
 def to_device_samples(samples: np.ndarray, device="cuda") -> torch.Tensor:
     return torch.from_numpy(np.ascontiguousarray(samples, dtype=np.float64)).to(device)
 
@@ -361,7 +504,8 @@ __all__ = [
     "Model", "ModelBatch", "harp_fit", "pack_model", "stack_models", "harp_fill",
     "harp_port_rhs", "harp_port_admittance", "reduced_factor", "reduced_solve", "Factors",
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
-    "to_device_samples", "default_grid",
+    "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
+    "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
 ]
 
 

@@ -1372,6 +1372,14 @@ extern "C" harp_status harp_debug_cgemm(harp_dtype dtype, int32_t M, int32_t N, 
                                         const void* d_A, int64_t lda, int64_t sA, const void* d_B, int64_t ldb,
                                         int64_t sB, double beta, const void* d_C, int64_t ldc, int64_t sC, void* d_D,
                                         int64_t ldd, int64_t sD, hipStream_t stream) {
+    return harp_cgemm(dtype, M, N, K, batch, alpha, d_A, lda, sA, d_B, ldb, sB, beta, d_C, ldc, sC, d_D, ldd, sD,
+                      stream);
+}
+
+extern "C" harp_status harp_cgemm(harp_dtype dtype, int32_t M, int32_t N, int32_t K, int32_t batch, double alpha,
+                                  const void* d_A, int64_t lda, int64_t sA, const void* d_B, int64_t ldb, int64_t sB,
+                                  double beta, const void* d_C, int64_t ldc, int64_t sC, void* d_D, int64_t ldd,
+                                  int64_t sD, hipStream_t stream) {
     if (M < 0 || N < 0 || K < 0 || batch <= 0 || batch > 65535 || !d_D) return HARP_E_ARG;
     if ((K > 0 && (!d_A || !d_B)) || (beta != 0.0 && !d_C)) return HARP_E_ARG;
     if (lda < std::max(1, M) || ldb < std::max(1, K) || ldd < std::max(1, M)) return HARP_E_ARG;

@@ -1,0 +1,179 @@
+"""GPU parity of the adjoint with respect to the antenna positions: the fill's
+and the patterns' vector-Jacobian products through the C ABI against the FP64
+oracle's, and the whole gradient of the synthesis objective (torch.autograd
+through ArrayResponse) at the 256-element station against the oracle's
+adjoint gradient and against central differences of the GPU forward."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as oadj  # noqa: E402
+from oracle import fit as ofit  # noqa: E402
+from workloads import directions, element, layout_disk, workload  # noqa: E402
+
+from parity import oracle_models, pack  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1702_03781_amd import api as A
+    return A
+
+
+def _crand(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _cm_cuda(api, M):
+    r, c = M.shape
+    T = api.colmajor(1, r, c, torch.complex128, "cuda")
+    T.copy_(torch.from_numpy(M)[None])
+    return T
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    """150 antennas (3 x 10 tiles of the adjoint kernel, ragged edges) of the
+    small element (4 MBFs), 120 MHz."""
+    el = element(4, 32, seed=201)
+    x, y = layout_disk(150, 14.0, 1.5, seed=909)
+    P, Q = 7, 6
+    m = ofit.fit(120e6, el.samples, P, Q, 1.5, wire_radius=el.wire_radius)
+    return x, y, m
+
+
+@pytest.mark.parametrize("ri", [0.0, 6.0])
+def test_fill_vjp_matches_oracle(api, ragged, ri):
+    x, y, m = ragged
+    n = x.size * m.n_mbf
+    W = _crand((n, n), 77)
+    mb = api.stack_models([pack(api, m)])
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    gx, gy, info = api.harp_fill_vjp(mb, xt, yt, _cm_cuda(api, W), ri=ri)
+    torch.cuda.synchronize()
+    assert int(info.cpu()[0]) == 0
+    ox, oy = oadj.fill_vjp(m, x, y, W, ri)
+    g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
+    o = np.concatenate([ox, oy])
+    assert np.linalg.norm(g - o) <= 1e-11 * np.linalg.norm(o)
+
+
+def test_fill_vjp_is_deterministic_and_rejects_mismatch(api, ragged):
+    x, y, m = ragged
+    n = x.size * m.n_mbf
+    W = _cm_cuda(api, _crand((n, n), 78))
+    mb = api.stack_models([pack(api, m)])
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    a = api.harp_fill_vjp(mb, xt, yt, W)[0].cpu().numpy()
+    b = api.harp_fill_vjp(mb, xt, yt, W)[0].cpu().numpy()
+    assert np.array_equal(a, b)
+    from paper_1702_03781_amd._lib import lib
+    gx = torch.zeros(x.size, dtype=torch.float64, device="cuda")
+    gy = torch.zeros_like(gx)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    info = torch.empty(1, dtype=torch.int32, device="cuda")
+    st = lib().harp_fill_vjp(mb.data.data_ptr(), m.n_mbf, m.Q + 1, xt.data_ptr(), yt.data_ptr(), x.size, 0.0,
+                             W.data_ptr(), n, gx.data_ptr(), gy.data_ptr(), info.data_ptr(), ws.data_ptr(),
+                             ws.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st == 0 and int(info.cpu()[0]) == -1
+
+
+def test_patterns_vjp_matches_oracle(api, ragged):
+    x, y, m = ragged
+    n, n_ports = x.size * m.n_mbf, 24
+    th, ph = directions(77, seed=11)
+    X = _crand((n, n_ports), 79)
+    gE = _crand((n_ports, th.size, 2), 80)
+    model = pack(api, m)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    Xt = _cm_cuda(api, X)
+    gX = api.colmajor(1, n, n_ports, torch.complex128, "cuda")
+    gX.zero_()
+    gx = torch.zeros(x.size, dtype=torch.float64, device="cuda")
+    gy = torch.zeros_like(gx)
+    api.embedded_patterns_vjp(model, xt, yt, Xt, torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda(),
+                              torch.from_numpy(gE).cuda(), gX, gx, gy)
+    torch.cuda.synchronize()
+    oX, ox, oy = oadj.patterns_vjp(m, x, y, X, th, ph, gE)
+    assert np.linalg.norm(gX[0].cpu().numpy() - oX) <= 1e-12 * np.linalg.norm(oX)
+    g = np.concatenate([gx.cpu().numpy(), gy.cpu().numpy()])
+    o = np.concatenate([ox, oy])
+    assert np.linalg.norm(g - o) <= 1e-11 * np.linalg.norm(o)
+
+
+def _objective_t(Y, E, w1, w2):
+    na = Y.shape[0]
+    zin = torch.diagonal(torch.linalg.inv(Y))
+    j1 = torch.sum(torch.abs(zin - 50.0) ** 2) / (na * 2500.0)
+    g = torch.mean(torch.sum(torch.abs(E) ** 2, dim=2), dim=0)
+    j2 = torch.var(g, unbiased=False) / torch.mean(g) ** 2
+    return w1 * j1 + w2 * j2
+
+
+@pytest.fixture(scope="module")
+def station(api):
+    """The adjoint configuration: the 256-element station at 110 MHz, 1024
+    directions, gradient with respect to all 512 coordinates."""
+    wl, models = oracle_models("cfg4")
+    m = models[0]
+    th, ph = wl.extra["theta"], wl.extra["phi"]
+    model = pack(api, m)
+    tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+    return wl, m, model, th, ph, tht, pht
+
+
+def _gpu_grad(api, station, w1, w2):
+    wl, m, model, th, ph, tht, pht = station
+    x = torch.from_numpy(wl.x.copy()).cuda().requires_grad_(True)
+    y = torch.from_numpy(wl.y.copy()).cuda().requires_grad_(True)
+    Y, E = api.array_response(x, y, model, tht, pht)
+    J = _objective_t(Y, E, w1, w2)
+    J.backward()
+    return float(J.detach()), x.grad.cpu().numpy(), y.grad.cpu().numpy()
+
+
+def _gpu_J(api, station, x, y, w1, w2):
+    wl, m, model, th, ph, tht, pht = station
+    with torch.no_grad():
+        Y, E = api.array_response(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), model, tht, pht)
+        return float(_objective_t(Y, E, w1, w2))
+
+
+@pytest.mark.parametrize("w1,w2", [(1.0, 1.0), (0.0, 1.0)])
+def test_station_gradient_matches_oracle(api, station, w1, w2):
+    wl, m, model, th, ph, *_ = station
+    J, gx, gy = _gpu_grad(api, station, w1, w2)
+    Yo, Eo, _, _ = oadj.response(m, wl.x, wl.y, th, ph)
+    assert abs(J - oadj.objective(Yo, Eo, w1, w2)) <= 1e-9 * abs(J)
+    ox, oy = oadj.gradient(m, wl.x, wl.y, th, ph, w1=w1, w2=w2)
+    g, o = np.concatenate([gx, gy]), np.concatenate([ox, oy])
+    assert np.linalg.norm(g - o) <= 1e-8 * np.linalg.norm(o)
+
+
+@pytest.mark.parametrize("w1,w2,h", [(0.0, 1.0, 1e-4), (1.0, 1.0, 1e-3)])
+def test_station_gradient_matches_finite_differences(api, station, w1, w2, h):
+    """Central differences of the GPU forward on 8 sampled coordinates; the
+    pattern term at h = 1e-4 m, the impedance-dominated total (J ~ 1e9, rounding
+    limits the differences below ~1e-3 m) at h = 1e-3 m."""
+    wl = station[0]
+    _, gx, gy = _gpu_grad(api, station, w1, w2)
+    g = np.concatenate([gx, gy])
+    coords = np.random.default_rng(2).choice(2 * wl.x.size, 8, replace=False)
+    fd = []
+    for c in coords:
+        x, y = wl.x.copy(), wl.y.copy()
+        v = x if c < wl.x.size else y
+        i = c % wl.x.size
+        v[i] += h
+        jp = _gpu_J(api, station, x, y, w1, w2)
+        v[i] -= 2 * h
+        jm = _gpu_J(api, station, x, y, w1, w2)
+        fd.append((jp - jm) / (2 * h))
+    fd = np.array(fd)
+    err = np.abs(fd - g[coords]).max() / np.abs(g).max()
+    assert err <= 1e-4, (err, fd, g[coords])
