@@ -92,6 +92,152 @@ def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
     }
 
 
+def roofline_from_prof(prof, steps):
+    """Roofline of the kernel class with the largest summed time, from the
+    library's dispatch-attached kernel timers."""
+    cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
+                                                    "trsm_lower", "trsm_upper")}
+    dom = max(cand, key=lambda k: cand[k]["ms"])
+    pd = prof[dom]
+    avg_ms = pd["ms"] / max(1, pd["launches"])
+    if dom == "fill":
+        bound, peak, unit = "alu", PEAK["fp64_vector_tflops"], "TFLOP/s"
+        achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
+    elif dom in ("gemm_c64", "gemm_c128"):
+        bound = "mfma"
+        peak = PEAK["fp32_mfma_tflops"] if dom == "gemm_c64" else PEAK["fp64_mfma_tflops"]
+        unit = "TFLOP/s"
+        achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
+    else:
+        bound, peak, unit, achieved = "latency", None, "TFLOP/s", None
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf) and dom in KERNEL_SOURCES:
+        try:
+            t = json.load(open(tf)).get(dom)
+            if t and t.get("source_sha") == _sha(KERNEL_SOURCES[dom]):
+                traffic = t.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    return {
+        "kernel": dom,
+        "bound": bound,
+        "achieved": achieved,
+        "peak": peak,
+        "unit": unit,
+        "frac": (achieved / peak) if (achieved and peak) else None,
+        "traffic": traffic,
+        "launches_per_step": pd["launches"] / steps,
+        "avg_launch_ms": avg_ms,
+        "algorithmic_flops_per_launch": pd["flops"] / max(1, pd["launches"]),
+        "algorithmic_bytes_per_launch": pd["bytes"] / max(1, pd["launches"]),
+    }
+
+
+def bench_batched(args, api, torch, dev):
+    """48 station layouts of 64-512 elements, each at 8 of the 16 sweep
+    frequencies (384 systems, n = 528-4056), reusing the 16 models."""
+    import numpy as np
+
+    from workloads import batched_layouts, workload
+
+    wl = workload("cfg2")        # element and frequency sweep whose models the layouts reuse
+    samples = api.to_device_samples(wl.elem.samples, dev)
+    models = [api.harp_fit(samples, wl.elem.wire_radius, f, P, wl.Q, wl.r_min)
+              for f, P in zip(wl.freqs, wl.P)]
+    mb = api.stack_models(models)
+    layouts = batched_layouts()
+    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams)
+    S.step()
+    torch.cuda.synchronize()
+    infos = [int(S.system(s)[2]) for s in range(S.n_systems)] + [int(S.system(s)[3])
+                                                                 for s in range(S.n_systems)]
+    if any(infos):
+        raise RuntimeError("fill domain error or zero pivot")
+    conv = all(r["converged"] for r in S.reports)
+    # accuracy gate on the smallest, a middle and the largest system: the
+    # refined batch against the plain complex128 GPU path of that layout alone
+    sizes = np.array(S.n_ant)
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    rel_x = rel_y = 0.0
+    for s in picks:
+        li, f = S.layout_of[s]
+        x, y, _ = layouts[li]
+        P = api.StationSolver(api.stack_models([models[f]]), torch.from_numpy(x).to(dev),
+                              torch.from_numpy(y).to(dev), "plain")
+        Xp, Yp = P.step()
+        X, Y, _, _ = S.system(s)
+        rel_x = max(rel_x, float(torch.linalg.norm(X - Xp[0]) / torch.linalg.norm(Xp[0])))
+        rel_y = max(rel_y, float(torch.linalg.norm(Y - Yp[0]) / torch.linalg.norm(Yp[0])))
+        del P, Xp, Yp
+    accuracy_ok = conv and rel_x <= REL_GATE and rel_y <= REL_GATE
+
+    for _ in range(args.warmup):
+        S.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    iters = sorted({r["iters"] for r in S.reports})
+
+    api.prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.step()
+    torch.cuda.synchronize()
+    ms_instr = (time.perf_counter() - t0) * 1e3 / args.steps
+    prof = api.prof_read()
+    api.prof_enable(False)
+    fill_flops_step = 0.0
+    for s in range(S.n_systems):
+        li, f = S.layout_of[s]
+        na_s = S.n_ant[s]
+        fill_flops_step += 2.0 * (2 * wl.P[f] + 1) * (2 * wl.Q + 4) * na_s * (na_s - 1) * wl.elem.n_mbf ** 2
+    prof["fill"]["flops"] = fill_flops_step * args.steps
+    for v in prof.values():
+        v["ms_per_step"] = v["ms"] / args.steps
+    roofline = roofline_from_prof(prof, args.steps)
+
+    nm = wl.elem.n_mbf
+    port_solves = float(sum(S.n_ant))
+    entries = float(sum((nm * v) ** 2 for v in S.n_ant))
+    padded = float(sum(len(g.members) * g.n ** 2 for g in S.groups))
+    out = {
+        "metric": "reduced-Z entries/s + port solves/s at rel err 1e-6 vs FP64 plain path",
+        "value": port_solves / (ms * 1e-3),
+        "unit": "port solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "ms_per_step_with_kernel_timers": ms_instr,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("batched layouts: 48 station layouts of 64-512 elements (disk radius "
+                         "19 m x sqrt(N_a/256), 1.5 m min spacing), 8 MBFs x 64 dipole samples, 8 of "
+                         "16 frequencies 50-350 MHz each (384 systems, n = 528-4056, N_a ports each); "
+                         "grouped and padded, complex64 LU on MFMA + FP64 refinement"),
+            "systems": S.n_systems, "groups": [(len(g.members), g.n) for g in S.groups],
+            "streams": args.streams, "refine_tol": args.tol,
+            "padded_over_real_entries": padded / entries,
+        },
+        "reduced_z_entries_per_s": entries / (ms * 1e-3),
+        "accuracy": {"max_rel_err_X_vs_plain": rel_x, "max_rel_err_Y_vs_plain": rel_y,
+                     "all_converged": conv, "gate": REL_GATE, "ok": accuracy_ok,
+                     "refine_iters": iters, "checked_systems": picks},
+        "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +247,10 @@ def main():
     ap.add_argument("--cpu-freqs", type=int, default=8,
                     help="frequencies in the CPU-baseline sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--workload", choices=["station", "batched"], default="station",
+                    help="station: the 16-frequency station sweep (default); batched: 48 unequal "
+                         "layouts x 8 frequencies")
+    ap.add_argument("--streams", type=int, default=2, help="HIP streams of the batched workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference kernel that "
                          "scales the HBM byte counters) and exit")
@@ -132,6 +282,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "copies": 3}))
         return
+    if args.workload == "batched":
+        return bench_batched(args, api, torch, dev)
     wl = workload("cfg2")
     n, na, nf = wl.n, wl.n_ant, len(wl.freqs)
 
@@ -199,44 +351,7 @@ def main():
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
 
-    # dominant kernel class and its roofline
-    cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
-                                                    "trsm_lower", "trsm_upper")}
-    dom = max(cand, key=lambda k: cand[k]["ms"])
-    pd = prof[dom]
-    avg_ms = pd["ms"] / max(1, pd["launches"])
-    if dom == "fill":
-        bound, peak, unit = "alu", PEAK["fp64_vector_tflops"], "TFLOP/s"
-        achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
-    elif dom in ("gemm_c64", "gemm_c128"):
-        bound = "mfma"
-        peak = PEAK["fp32_mfma_tflops"] if dom == "gemm_c64" else PEAK["fp64_mfma_tflops"]
-        unit = "TFLOP/s"
-        achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
-    else:
-        bound, peak, unit, achieved = "latency", None, "TFLOP/s", None
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf) and dom in KERNEL_SOURCES:
-        try:
-            t = json.load(open(tf)).get(dom)
-            if t and t.get("source_sha") == _sha(KERNEL_SOURCES[dom]):
-                traffic = t.get("hbm_bytes_per_launch")
-        except Exception:
-            traffic = None
-    roofline = {
-        "kernel": dom,
-        "bound": bound,
-        "achieved": achieved,
-        "peak": peak,
-        "unit": unit,
-        "frac": (achieved / peak) if (achieved and peak) else None,
-        "traffic": traffic,
-        "launches_per_step": pd["launches"] / args.steps,
-        "avg_launch_ms": avg_ms,
-        "algorithmic_flops_per_launch": pd["flops"] / max(1, pd["launches"]),
-        "algorithmic_bytes_per_launch": pd["bytes"] / max(1, pd["launches"]),
-    }
+    roofline = roofline_from_prof(prof, args.steps)
 
     port_solves = nf * na
     value = port_solves / (ms * 1e-3)

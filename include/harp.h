@@ -136,6 +136,68 @@ harp_status harp_fill(const void *d_models, int64_t model_stride, int32_t n_freq
                       int32_t *d_info, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batches of unequal layouts (many layouts and frequencies reusing one      */
+/* model per element and frequency, Section II-D, Section III-C)            */
+/* ------------------------------------------------------------------------ */
+
+/* One system of a batch: the layout of n_ant antennas whose positions are
+ * x[pos .. pos + n_ant), y[same), evaluated with model blob number `model`. */
+typedef struct {
+    int32_t model;
+    int32_t n_ant;
+    int64_t pos;
+} harp_system;
+
+/* Grouping plan (host only, no device work).  The n_sys systems (antenna
+ * counts n_ant[], host) are sorted by size (stable) and cut into contiguous
+ * groups; each group is padded to the antenna count of its largest system
+ * rounded up to a multiple of pad_multiple, with padded order
+ * N = n_pad * n_mbf <= max_order, and holds at most max_batch systems.  The
+ * cut minimises the modelled time sum over groups of
+ * cost[0] + cost[1] N + cost[2] c N^3 (c systems in the group; cost == NULL
+ * takes built-in defaults measured on MI355X).  Outputs (host, caller-owned):
+ * order[n_sys] the system indices in group order, group_begin[n_groups + 1]
+ * (capacity n_sys + 1) offsets into order, group_pad[n_groups] (capacity
+ * n_sys) the padded antenna count, *n_groups.  HARP_E_ARG on a non-positive
+ * count or a system whose padded order exceeds max_order. */
+harp_status harp_batch_plan(const int32_t *n_ant, int32_t n_sys, int32_t n_mbf, int32_t pad_multiple,
+                            int32_t max_order, int32_t max_batch, const double *cost, int32_t *order,
+                            int32_t *group_begin, int32_t *group_pad, int32_t *n_groups);
+
+/* harp_fill for a group of n_sys systems (d_sys, device, [n_sys]) padded to
+ * n_ant_pad antennas: matrix s (order N = n_ant_pad * n_mbf) holds the Eq. (4)
+ * fill of system s in its leading n x n block (n = its n_ant * n_mbf) and the
+ * identity in the trailing N - n rows and columns (zeros elsewhere), so that
+ * its LU and its solution for right-hand sides padded with zeros are those of
+ * the layout, padded.  Model blobs d_models[0 .. n_models), n_pos positions in
+ * d_x, d_y.  d_info[s] as for harp_fill, or -2 if descriptor s is out of range
+ * (model index, n_ant not in [1, n_ant_pad], positions beyond n_pos; nothing
+ * is written to that matrix).  Asynchronous. */
+harp_status harp_fill_systems(const void *d_models, int64_t model_stride, int32_t n_models,
+                              int32_t n_mbf, int32_t Q, int32_t p_max, const double *d_x,
+                              const double *d_y, int64_t n_pos, const harp_system *d_sys,
+                              int32_t n_sys, int32_t n_ant_pad, double ri, harp_dtype dtype, void *d_Z,
+                              int64_t ldz, int64_t stride_z, void *d_Z32, int64_t ld32,
+                              int64_t stride32, int32_t *d_info, hipStream_t stream);
+
+/* harp_port_rhs for a padded group: B_s (complex128, N x n_ant_pad) holds the
+ * unit excitation of the system's ports (its model's weights) in its leading
+ * n x n_ant block and zeros elsewhere (a descriptor out of range gives zeros). */
+harp_status harp_port_rhs_systems(const void *d_models, int64_t model_stride, int32_t n_models,
+                                  int32_t n_mbf, const harp_system *d_sys, int32_t n_sys,
+                                  int32_t n_ant_pad, void *d_B, int64_t ldb, int64_t stride_b,
+                                  hipStream_t stream);
+
+/* harp_port_admittance for a padded group: Y_s (complex128,
+ * n_ant_pad x n_ant_pad) = W^T X in its leading n_ant x n_ant block, zeros
+ * elsewhere. */
+harp_status harp_port_admittance_systems(const void *d_models, int64_t model_stride, int32_t n_models,
+                                         int32_t n_mbf, const harp_system *d_sys, int32_t n_sys,
+                                         int32_t n_ant_pad, const void *d_X, int64_t ldx,
+                                         int64_t stride_x, void *d_Y, int64_t ldy, int64_t stride_y,
+                                         hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* Ports (Sections I and II-C)                                               */
 /* ------------------------------------------------------------------------ */
 

@@ -19,6 +19,8 @@ c_dbl = ctypes.c_double
 c_sz = ctypes.c_size_t
 c_vp = ctypes.c_void_p
 c_szp = ctypes.POINTER(ctypes.c_size_t)
+c_i32p = ctypes.POINTER(ctypes.c_int32)
+c_dblp = ctypes.POINTER(ctypes.c_double)
 
 
 class HarpElement(ctypes.Structure):
@@ -44,6 +46,14 @@ SIGNATURES = {
                          c_vp, c_sz, c_vp, c_sz, c_vp]),
     "harp_fill": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_dbl, c_i32,
                           c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "harp_batch_plan": (c_i32, [c_i32p, c_i32, c_i32, c_i32, c_i32, c_i32, c_dblp, c_i32p, c_i32p,
+                                c_i32p, c_i32p]),
+    "harp_fill_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_i64, c_vp, c_i32,
+                                  c_i32, c_dbl, c_i32, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "harp_port_rhs_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_i64,
+                                      c_vp]),
+    "harp_port_admittance_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64,
+                                             c_i64, c_vp, c_i64, c_i64, c_vp]),
     "harp_port_rhs": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp]),
     "harp_port_admittance": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp,
                                      c_i64, c_i64, c_vp]),

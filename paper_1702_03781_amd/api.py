@@ -506,6 +506,8 @@ __all__ = [
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
     "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
+    "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "harp_fill_systems", "harp_port_rhs_systems",
+    "harp_port_admittance_systems", "BatchSolver", "StationSolver",
 ]
 
 
@@ -583,6 +585,222 @@ class StationSolver:
             self.reports = [{"iters": r.iters, "converged": bool(r.converged),
                              "resid_rel": r.resid_rel} for r in rep]
         return self.X, self.Y
+
+
+# --------------------------------------------------------------------------
+# batches of unequal layouts
+# --------------------------------------------------------------------------
+
+SYSTEM_DTYPE = np.dtype([("model", "<i4"), ("n_ant", "<i4"), ("pos", "<i8")])   # harp_system
+
+
+def systems_tensor(model_idx, n_ant, pos, device="cuda") -> torch.Tensor:
+    """Device array of harp_system descriptors (16 bytes each)."""
+    a = np.zeros(len(model_idx), dtype=SYSTEM_DTYPE)
+    a["model"], a["n_ant"], a["pos"] = model_idx, n_ant, pos
+    return torch.from_numpy(a.view(np.uint8).copy()).to(device)
+
+
+def harp_batch_plan(n_ant, n_mbf: int, pad_multiple: int = 8, max_order: int = 8192,
+                    max_batch: int = 96, cost=None):
+    """Grouping of unequal systems: (order, groups), groups = [(begin, end,
+    n_ant_pad)] indexing `order` (system indices sorted by size)."""
+    n = len(n_ant)
+    na = (ctypes.c_int32 * n)(*[int(v) for v in n_ant])
+    order = (ctypes.c_int32 * n)()
+    gb = (ctypes.c_int32 * (n + 1))()
+    gp = (ctypes.c_int32 * n)()
+    ng = ctypes.c_int32()
+    c = (ctypes.c_double * 3)(*cost) if cost is not None else None
+    check(lib().harp_batch_plan(na, n, n_mbf, pad_multiple, max_order, max_batch, c, order, gb, gp,
+                                ctypes.byref(ng)), "harp_batch_plan")
+    groups = [(gb[g], gb[g + 1], gp[g]) for g in range(ng.value)]
+    return list(order), groups
+
+
+def harp_fill_systems(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, sys: torch.Tensor,
+                      n_ant_pad: int, dtype="c128", ri: float = 0.0, Z: torch.Tensor | None = None,
+                      Z32: torch.Tensor | None = None, dual: bool = False):
+    """Fill a group of systems padded to n_ant_pad antennas.  Returns (Z, Z32, info)."""
+    dt = _DT[dtype]
+    dev = models.data.device
+    n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
+    n = n_ant_pad * models.n_mbf
+    if Z is None:
+        Z = colmajor(n_sys, n, n, _TORCH_DT[dt], dev)
+    if dual and Z32 is None:
+        Z32 = colmajor(n_sys, n, n, torch.complex64, dev)
+    pz, ldz, sz = _cm(Z, "Z")
+    p32, ld32, s32 = _cm(Z32, "Z32") if Z32 is not None else (0, 0, 0)
+    info = torch.empty(n_sys, dtype=torch.int32, device=dev)
+    x, y = x.contiguous(), y.contiguous()
+    check(lib().harp_fill_systems(_ptr(models.data), models.stride, models.n_freq, models.n_mbf, models.Q,
+                                  models.p_max, _ptr(x), _ptr(y), int(x.numel()), _ptr(sys), n_sys, n_ant_pad,
+                                  float(ri), dt, pz, ldz, sz, p32, ld32, s32, _ptr(info), _stream(dev)),
+          "harp_fill_systems")
+    return Z, Z32, info
+
+
+def harp_port_rhs_systems(models: ModelBatch, sys: torch.Tensor, n_ant_pad: int,
+                          B: torch.Tensor | None = None):
+    dev = models.data.device
+    n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
+    n = n_ant_pad * models.n_mbf
+    if B is None:
+        B = colmajor(n_sys, n, n_ant_pad, torch.complex128, dev)
+    pb, ldb, sb = _cm(B, "B")
+    check(lib().harp_port_rhs_systems(_ptr(models.data), models.stride, models.n_freq, models.n_mbf, _ptr(sys),
+                                      n_sys, n_ant_pad, pb, ldb, sb, _stream(dev)), "harp_port_rhs_systems")
+    return B
+
+
+def harp_port_admittance_systems(models: ModelBatch, sys: torch.Tensor, X: torch.Tensor,
+                                 Y: torch.Tensor | None = None):
+    dev = models.data.device
+    n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
+    n_ant_pad = X.shape[-1]
+    if Y is None:
+        Y = colmajor(n_sys, n_ant_pad, n_ant_pad, torch.complex128, dev)
+    px, ldx, sx = _cm(X, "X")
+    py, ldy, sy = _cm(Y, "Y")
+    check(lib().harp_port_admittance_systems(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
+                                             _ptr(sys), n_sys, n_ant_pad, px, ldx, sx, py, ldy, sy,
+                                             _stream(dev)), "harp_port_admittance_systems")
+    return Y
+
+
+class _Group:
+    """Device buffers of one padded group (refined path)."""
+
+    def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, dev):
+        self.members, self.n_pad = members, n_pad
+        c = len(members)
+        n = self.n = n_pad * models.n_mbf
+        self.sys = systems_tensor([model_idx[i] for i in members], [n_ant[i] for i in members],
+                                  [pos[i] for i in members], dev)
+        self.Z64 = colmajor(c, n, n, torch.complex128, dev)
+        self.Z32 = colmajor(c, n, n, torch.complex64, dev)
+        self.B = colmajor(c, n, n_pad, torch.complex128, dev)
+        self.X = colmajor(c, n, n_pad, torch.complex128, dev)
+        self.Y = colmajor(c, n_pad, n_pad, torch.complex128, dev)
+        self.info = torch.empty(c, dtype=torch.int32, device=dev)
+        self.finfo = torch.empty(c, dtype=torch.int32, device=dev)
+        self.ipiv = torch.empty((c, n), dtype=torch.int32, device=dev)
+        b = ctypes.c_size_t()
+        check(lib().reduced_factor_ws(n, c, C64, ctypes.byref(b)), "reduced_factor_ws")
+        self.aux, self.aux_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
+        check(lib().reduced_solve_ws(n, n_pad, c, C64, 1, ctypes.byref(b)), "reduced_solve_ws")
+        self.ws, self.ws_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
+
+
+class BatchSolver:
+    """The refined hot path (FP64 fill written as complex128 and complex64,
+    complex64 LU, solve, FP64 refinement, admittances) for a batch of
+    unequal layouts, each at several frequencies, reusing one model per
+    frequency.  Systems are grouped by harp_batch_plan and padded per group;
+    groups are issued round-robin on `streams` HIP streams (default
+    priority), all buffers allocated once."""
+
+    def __init__(self, models: ModelBatch, layouts, tol: float = 1e-10, max_iter: int = 10,
+                 streams: int = 1, ri: float = 0.0, **plan_kw):
+        dev = models.data.device
+        self.models, self.tol, self.max_iter, self.ri = models, tol, max_iter, ri
+        xs, ys, model_idx, n_ant, pos, self.layout_of = [], [], [], [], [], []
+        off = 0
+        for li, (x, y, fidx) in enumerate(layouts):
+            xs.append(np.asarray(x, dtype=np.float64))
+            ys.append(np.asarray(y, dtype=np.float64))
+            for f in fidx:
+                model_idx.append(int(f))
+                n_ant.append(int(xs[-1].size))
+                pos.append(off)
+                self.layout_of.append((li, int(f)))
+            off += xs[-1].size
+        self.x = torch.from_numpy(np.concatenate(xs)).to(dev)
+        self.y = torch.from_numpy(np.concatenate(ys)).to(dev)
+        self.n_ant = n_ant
+        order, groups = harp_batch_plan(n_ant, models.n_mbf, **plan_kw)
+        self.groups = [_Group(models, order[b:e], pad, model_idx, n_ant, pos, dev) for b, e, pad in groups]
+        self.where = {}
+        for gi, g in enumerate(self.groups):
+            for k, s in enumerate(g.members):
+                self.where[s] = (gi, k)
+        self.streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(streams - 1)]
+        self.reports = None
+
+    @property
+    def n_systems(self) -> int:
+        return len(self.n_ant)
+
+    def _front(self, g: _Group, st: int):
+        L, mb = lib(), self.models
+        c = len(g.members)
+        pz, ldz, sz = _cm(g.Z64, "Z64")
+        p32, ld32, s32 = _cm(g.Z32, "Z32")
+        check(L.harp_fill_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
+                                  _ptr(self.y), int(self.x.numel()), _ptr(g.sys), c, g.n_pad, float(self.ri),
+                                  C128, pz, ldz, sz, p32, ld32, s32, _ptr(g.info), st), "harp_fill_systems")
+        pb, ldb, sb = _cm(g.B, "B")
+        check(L.harp_port_rhs_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c, g.n_pad,
+                                      pb, ldb, sb, st), "harp_port_rhs_systems")
+        check(L.reduced_factor(g.n, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.finfo), _ptr(g.aux),
+                               g.aux_bytes, st), "reduced_factor")
+
+    def _back(self, g: _Group, st: int):
+        L, mb = lib(), self.models
+        c = len(g.members)
+        pz, ldz, sz = _cm(g.Z64, "Z64")
+        p32, ld32, s32 = _cm(g.Z32, "Z32")
+        pb, ldb, sb = _cm(g.B, "B")
+        px, ldx, sx = _cm(g.X, "X")
+        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter))
+        rep = (HarpRefineReport * c)()
+        check(L.reduced_solve(g.n, g.n_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux), g.aux_bytes,
+                              pb, ldb, sb, px, ldx, sx, ctypes.byref(ref), rep, _ptr(g.ws), g.ws_bytes, st),
+              "reduced_solve")
+        py, ldy, sy = _cm(g.Y, "Y")
+        check(L.harp_port_admittance_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c,
+                                             g.n_pad, px, ldx, sx, py, ldy, sy, st),
+              "harp_port_admittance_systems")
+        return rep
+
+    def step(self):
+        """One pass over every system.  Fill, excitation and factorisation of
+        all groups are enqueued first; the solves (which synchronise their
+        stream once per refinement sweep) follow group by group."""
+        sts = [s.cuda_stream for s in self.streams]
+        if len(self.streams) > 1:
+            ev = torch.cuda.Event()
+            ev.record(self.streams[0])
+            for s in self.streams[1:]:
+                s.wait_event(ev)
+        for gi, g in enumerate(self.groups):
+            self._front(g, sts[gi % len(sts)])
+        reports = [None] * self.n_systems
+        for gi, g in enumerate(self.groups):
+            rep = self._back(g, sts[gi % len(sts)])
+            for k, s in enumerate(g.members):
+                reports[s] = {"iters": rep[k].iters, "converged": bool(rep[k].converged),
+                              "resid_rel": rep[k].resid_rel}
+        for s in self.streams[1:]:
+            ev = torch.cuda.Event()
+            ev.record(s)
+            self.streams[0].wait_event(ev)
+        self.reports = reports
+
+    def system(self, s: int):
+        """(X, Y, fill info, factor info) of system s, unpadded views."""
+        gi, k = self.where[s]
+        g = self.groups[gi]
+        na = self.n_ant[s]
+        n = na * self.models.n_mbf
+        return g.X[k, :n, :na], g.Y[k, :na, :na], g.info[k], g.finfo[k]
+
+    def padded(self, s: int):
+        """(Z64, X, Y) of system s with its padding."""
+        gi, k = self.where[s]
+        g = self.groups[gi]
+        return g.Z64[k], g.X[k], g.Y[k]
 
 
 def prof_enable(on: bool) -> None:

@@ -38,7 +38,7 @@ constexpr int kTileN = 4 * kG;
 struct FillArgs {
     const char* models;
     int64_t model_stride;
-    int n_freq, n_mbf, Q, p_max, n_ant;
+    int n_freq, n_mbf, Q, p_max, n_ant;  // n_freq: matrices; n_ant: antennas of the (padded) order
     const double* x;
     const double* y;
     double ri;
@@ -47,6 +47,10 @@ struct FillArgs {
     float* Z32;
     int64_t ld32, stride32;
     int32_t* info;
+    // batch of unequal layouts (nullptr: matrix f uses model f, all n_ant antennas at x[0..))
+    const harp_system* sys;
+    int n_models;
+    int64_t n_pos;
 };
 
 __global__ void fill_info_init(int32_t* info, int n) {
@@ -68,7 +72,8 @@ template <> struct FillTraits<double> {
     }
 };
 
-enum PairKind : int { kSkip = 0, kHarp = 1, kSelf = 2, kZero = 3 };
+// kPad: identity block of a padding antenna (unit diagonal, zeros elsewhere)
+enum PairKind : int { kSkip = 0, kHarp = 1, kSelf = 2, kZero = 3, kPad = 4 };
 
 // The pointers are separate __restrict__ parameters (not struct members) so
 // that the compiler may read the model through the scalar cache.
@@ -77,7 +82,21 @@ __global__ void __launch_bounds__(256)
     fill_kernel(FillArgs a, const char* __restrict__ models, const double* __restrict__ px,
                 const double* __restrict__ py, void* __restrict__ Zout, float* __restrict__ Z32out) {
     const int f = blockIdx.y;
-    const char* model = models + size_t(f) * a.model_stride;
+    // antennas of this system (ns <= a.n_ant; the rest of the order is padding)
+    int mi = f, ns = a.n_ant;
+    if (a.sys) {
+        const harp_system d = a.sys[f];
+        if (d.model < 0 || d.model >= a.n_models || d.n_ant < 1 || d.n_ant > a.n_ant || d.pos < 0 ||
+            d.pos > a.n_pos - d.n_ant) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.info + f, -2);
+            return;
+        }
+        mi = d.model;
+        ns = d.n_ant;
+        px += d.pos;
+        py += d.pos;
+    }
+    const char* model = models + size_t(mi) * a.model_stride;
     const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
     const int P = h->P;
     if (h->magic != kModelMagic || h->n_mbf != a.n_mbf || h->Q != Q || P > a.p_max || P < 0) {
@@ -97,8 +116,8 @@ __global__ void __launch_bounds__(256)
     R t[kG];
     cpx<R> w[kG], ph[kG];
     int n_below = 0;
-    const double xm = m < a.n_ant ? px[m] : 0.0;
-    const double ym = m < a.n_ant ? py[m] : 0.0;
+    const double xm = m < ns ? px[m] : 0.0;
+    const double ym = m < ns ? py[m] : 0.0;
 #pragma unroll
     for (int g = 0; g < kG; ++g) {
         const int n = tn * kTileN + wave * kG + g;
@@ -107,6 +126,10 @@ __global__ void __launch_bounds__(256)
         w[g] = cpx<R>{R(1), R(0)};
         ph[g] = cpx<R>{R(0), R(0)};
         if (m >= a.n_ant || n >= a.n_ant) continue;
+        if (m >= ns || n >= ns) {
+            kind[g] = m == n ? kPad : kZero;
+            continue;
+        }
         if (m == n) {
             kind[g] = kSelf;
             continue;
@@ -192,6 +215,8 @@ __global__ void __launch_bounds__(256)
                     z = cmul(acc[g], ph[g]);
                 } else if (kind[g] == kSelf) {
                     z = cpx<R>{R(sr), R(si)};
+                } else if (kind[g] == kPad) {
+                    z = cpx<R>{R(T == S ? 1 : 0), R(0)};
                 } else {
                     z = cpx<R>{R(0), R(0)};
                 }
@@ -238,32 +263,37 @@ harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
     return HARP_OK;
 }
 
-}  // namespace
-}  // namespace harp
-
-using namespace harp;
-
-extern "C" harp_status harp_fill(const void* d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
-                                 int32_t Q, int32_t p_max, const double* d_x, const double* d_y,
-                                 int32_t n_ant, double ri, harp_dtype dtype, void* d_Z, int64_t ldz,
-                                 int64_t stride_z, void* d_Z32, int64_t ld32, int64_t stride32,
-                                 int32_t* d_info, hipStream_t stream) {
-    if (!d_models || !d_x || !d_y || !d_Z || !d_info) return HARP_E_ARG;
-    if (n_freq <= 0 || n_mbf <= 0 || n_ant <= 0 || Q < 2 || Q > 8 || p_max < 0) return HARP_E_ARG;
-    if (n_freq > 65535) return HARP_E_ARG;
+harp_status fill_launch(FillArgs& a, harp_dtype dtype, hipStream_t stream) {
+    if (!a.models || !a.x || !a.y || !a.Z || !a.info) return HARP_E_ARG;
+    if (a.n_freq <= 0 || a.n_mbf <= 0 || a.n_ant <= 0 || a.Q < 2 || a.Q > 8 || a.p_max < 0) return HARP_E_ARG;
+    if (a.n_freq > 65535) return HARP_E_ARG;
     if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
-    if (!isfinite(ri)) return HARP_E_ARG;
-    const int64_t n = int64_t(n_ant) * n_mbf;
-    if (ldz < n || (n_freq > 1 && stride_z < ldz * n)) return HARP_E_ARG;
-    if (model_stride < 256 || (model_stride % 256) != 0) return HARP_E_ARG;
-    if (d_Z32) {
+    if (!isfinite(a.ri)) return HARP_E_ARG;
+    const int64_t n = int64_t(a.n_ant) * a.n_mbf;
+    if (a.ldz < n || (a.n_freq > 1 && a.stride_z < a.ldz * n)) return HARP_E_ARG;
+    if (a.model_stride < 256 || (a.model_stride % 256) != 0) return HARP_E_ARG;
+    if (a.Z32) {
         if (dtype != HARP_C128) return HARP_E_ARG;
-        if (ld32 < n || (n_freq > 1 && stride32 < ld32 * n)) return HARP_E_ARG;
+        if (a.ld32 < n || (a.n_freq > 1 && a.stride32 < a.ld32 * n)) return HARP_E_ARG;
     }
-    FillArgs a;
+    HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
+                     hipLaunchKernelGGL(fill_info_init, dim3((a.n_freq + 255) / 256), dim3(256), 0, stream, a.info,
+                                        a.n_freq));
+    HARP_LAUNCH_CHECK();
+    const int tiles = ((a.n_ant + kTileM - 1) / kTileM) * ((a.n_ant + kTileN - 1) / kTileN);
+    const dim3 grid{unsigned(tiles), unsigned(a.n_freq), 1u};
+    if (dtype == HARP_C64) return launch_fill_q<float, false>(a, grid, stream);
+    if (a.Z32) return launch_fill_q<double, true>(a, grid, stream);
+    return launch_fill_q<double, false>(a, grid, stream);
+}
+
+FillArgs fill_args(const void* d_models, int64_t model_stride, int32_t n_mat, int32_t n_mbf, int32_t Q,
+                   int32_t p_max, const double* d_x, const double* d_y, int32_t n_ant, double ri, void* d_Z,
+                   int64_t ldz, int64_t stride_z, void* d_Z32, int64_t ld32, int64_t stride32, int32_t* d_info) {
+    FillArgs a{};
     a.models = static_cast<const char*>(d_models);
     a.model_stride = model_stride;
-    a.n_freq = n_freq;
+    a.n_freq = n_mat;
     a.n_mbf = n_mbf;
     a.Q = Q;
     a.p_max = p_max;
@@ -278,13 +308,35 @@ extern "C" harp_status harp_fill(const void* d_models, int64_t model_stride, int
     a.ld32 = ld32;
     a.stride32 = stride32;
     a.info = d_info;
-    HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
-                     hipLaunchKernelGGL(fill_info_init, dim3((n_freq + 255) / 256), dim3(256), 0, stream, d_info,
-                                        n_freq));
-    HARP_LAUNCH_CHECK();
-    const int tiles = ((n_ant + kTileM - 1) / kTileM) * ((n_ant + kTileN - 1) / kTileN);
-    const dim3 grid{unsigned(tiles), unsigned(n_freq), 1u};
-    if (dtype == HARP_C64) return launch_fill_q<float, false>(a, grid, stream);
-    if (d_Z32) return launch_fill_q<double, true>(a, grid, stream);
-    return launch_fill_q<double, false>(a, grid, stream);
+    return a;
+}
+
+}  // namespace
+}  // namespace harp
+
+using namespace harp;
+
+extern "C" harp_status harp_fill(const void* d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
+                                 int32_t Q, int32_t p_max, const double* d_x, const double* d_y,
+                                 int32_t n_ant, double ri, harp_dtype dtype, void* d_Z, int64_t ldz,
+                                 int64_t stride_z, void* d_Z32, int64_t ld32, int64_t stride32,
+                                 int32_t* d_info, hipStream_t stream) {
+    FillArgs a = fill_args(d_models, model_stride, n_freq, n_mbf, Q, p_max, d_x, d_y, n_ant, ri, d_Z, ldz, stride_z,
+                           d_Z32, ld32, stride32, d_info);
+    return fill_launch(a, dtype, stream);
+}
+
+extern "C" harp_status harp_fill_systems(const void* d_models, int64_t model_stride, int32_t n_models,
+                                         int32_t n_mbf, int32_t Q, int32_t p_max, const double* d_x,
+                                         const double* d_y, int64_t n_pos, const harp_system* d_sys,
+                                         int32_t n_sys, int32_t n_ant_pad, double ri, harp_dtype dtype, void* d_Z,
+                                         int64_t ldz, int64_t stride_z, void* d_Z32, int64_t ld32,
+                                         int64_t stride32, int32_t* d_info, hipStream_t stream) {
+    if (!d_sys || n_models <= 0 || n_pos <= 0) return HARP_E_ARG;
+    FillArgs a = fill_args(d_models, model_stride, n_sys, n_mbf, Q, p_max, d_x, d_y, n_ant_pad, ri, d_Z, ldz,
+                           stride_z, d_Z32, ld32, stride32, d_info);
+    a.sys = d_sys;
+    a.n_models = n_models;
+    a.n_pos = n_pos;
+    return fill_launch(a, dtype, stream);
 }

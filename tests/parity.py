@@ -7,7 +7,7 @@ import functools
 
 import numpy as np
 
-from oracle import em, fit as ofit
+from oracle import em, fill as ofill, fit as ofit
 from workloads import workload
 
 
@@ -53,3 +53,23 @@ def pack(api, m, device="cuda"):
 def colmajor_to_numpy(M) -> np.ndarray:
     """Batched column-major torch view (b, rows, cols) -> numpy (b, rows, cols)."""
     return M.detach().cpu().numpy()
+
+
+def oracle_fill_chunked(model, x, y, ri: float = 0.0, chunk: int = 32768) -> np.ndarray:
+    """The oracle fill (same numbers as oracle.fill.fill) with the model
+    evaluated in chunks of pairs, and blocks beyond a radius of influence left
+    at zero without evaluating them (bounded memory at n ~ 8192)."""
+    na, nm = x.size, model.n_mbf
+    Z = np.zeros((na, nm, na, nm), dtype=np.complex128)
+    mm, nn = np.meshgrid(np.arange(na), np.arange(na), indexing="ij")
+    sel = mm != nn
+    if ri > 0.0:
+        d = np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :])
+        sel &= d <= ri
+    Rx, Ry = (x[:, None] - x[None, :])[sel], (y[:, None] - y[None, :])[sel]
+    blocks = np.concatenate([ofill.eval_model(model, Rx[i:i + chunk], Ry[i:i + chunk])
+                             for i in range(0, Rx.size, chunk)])
+    Z[mm[sel], :, nn[sel], :] = blocks
+    for m in range(na):
+        Z[m, :, m, :] = model.Z_self
+    return Z.reshape(na * nm, na * nm)

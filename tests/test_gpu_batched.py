@@ -1,0 +1,159 @@
+"""GPU parity of the batch of unequal layouts (grouping plan, padded fill,
+per-system ports, complex64 LU with FP64 refinement) through the C ABI.
+
+Small batch: six layouts of 5..37 elements (ragged, padded to multiples of
+8 antennas, at most two systems per group so several groups are formed), each
+at one or two of three frequencies, on one and on two streams -- every system
+against the FP64 oracle (fill per block, X and Y against LAPACK), the padding
+exactly the identity / zero.
+Batched layouts: 48 station layouts of 64..512 elements, 8 of the 16 sweep
+frequencies each (384 systems, n = 528..4056), as timed -- every system by
+recomputed residual, reciprocity and exact padding, and the smallest, a middle
+and the largest system against the oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fill as ofill, fit as ofit, solve as osolve  # noqa: E402
+from workloads import batched_layouts, element, layout_disk  # noqa: E402
+
+from parity import block_eps, oracle_fill_chunked, oracle_models, pack  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1702_03781_amd import api as A
+    return A
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _port_rel(a, b):
+    return float((np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max())
+
+
+@pytest.fixture(scope="module")
+def small(api):
+    el = element(4, 32, seed=201)
+    freqs = [100e6, 130e6, 170e6]
+    models = [ofit.fit(f, el.samples, 7, 6, 1.5, wire_radius=el.wire_radius) for f in freqs]
+    layouts = []
+    for i, na in enumerate([5, 9, 16, 23, 37, 12]):
+        x, y = layout_disk(na, 1.5 + 1.2 * np.sqrt(na), 1.5, seed=500 + i)
+        layouts.append((x, y, [i % 3] if i % 2 else [0, 2]))
+    mb = api.stack_models([pack(api, m) for m in models])
+    return models, layouts, mb
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_batched_small_matches_oracle(api, small, streams):
+    models, layouts, mb = small
+    S = api.BatchSolver(mb, layouts, tol=1e-10, streams=streams, max_batch=2)
+    S.step()
+    torch.cuda.synchronize()
+    assert len(S.groups) >= 3
+    s = 0
+    for x, y, fidx in layouts:
+        for f in fidx:
+            m = models[f]
+            na, n = x.size, x.size * m.n_mbf
+            X, Y, info, finfo = S.system(s)
+            assert int(info) == 0 and int(finfo) == 0, s
+            assert S.reports[s]["converged"], S.reports[s]
+            Zp, Xp, Yp = (t.cpu().numpy() for t in S.padded(s))
+            N = Zp.shape[0]
+            Zo = ofill.fill(m, x, y)
+            eps, zero_ok, _ = block_eps(Zp[:n, :n], Zo, m.n_mbf)
+            assert eps <= 1e-12 and zero_ok, (s, eps)
+            for a in range(na):
+                blk = slice(a * m.n_mbf, (a + 1) * m.n_mbf)
+                assert np.array_equal(Zp[blk, blk], m.Z_self)
+            assert (Zp[n:, :n] == 0).all() and (Zp[:n, n:] == 0).all()
+            assert np.array_equal(Zp[n:, n:], np.eye(N - n))
+            Bo = osolve.port_rhs(m.w, na)
+            Xo = osolve.solve(Zo, Bo)
+            Yo = osolve.admittance(Xo, m.w, na)
+            assert _port_rel(X.cpu().numpy(), Xo) <= 1e-6
+            assert _rel(Y.cpu().numpy(), Yo) <= 1e-6
+            assert (Xp[n:, :] == 0).all() and (Xp[:, na:] == 0).all()
+            assert (Yp[na:, :] == 0).all() and (Yp[:, na:] == 0).all()
+            s += 1
+    # the complex64 copy written beside the FP64 fill is its rounding (the
+    # solver's own copy holds the LU factors by now)
+    g = S.groups[-1]
+    Z64, Z32, info = api.harp_fill_systems(mb, S.x, S.y, g.sys, g.n_pad, dtype="c128", dual=True)
+    torch.cuda.synchronize()
+    assert not info.any() and torch.equal(Z64, g.Z64) and torch.equal(Z32, Z64.to(torch.complex64))
+
+
+def test_bad_descriptor_is_reported(api, small):
+    models, layouts, mb = small
+    x = torch.from_numpy(layouts[0][0]).cuda()
+    y = torch.from_numpy(layouts[0][1]).cuda()
+    na = x.numel()
+    sys = api.systems_tensor([0, 5, 1, 0], [na, na, na + 1, na], [0, 0, 0, 1], "cuda")
+    _, _, info = api.harp_fill_systems(mb, x, y, sys, na + 1, dtype="c128")
+    torch.cuda.synchronize()
+    # model 5 out of range; positions [0, na+1) and [1, na+1) beyond the array
+    assert info.cpu().tolist() == [0, -2, -2, -2]
+
+
+@pytest.fixture(scope="module")
+def batched(api):
+    wl, models = oracle_models("cfg2")
+    mb = api.stack_models([pack(api, m) for m in models])
+    layouts = batched_layouts()
+    S = api.BatchSolver(mb, layouts, tol=1e-10, streams=2)
+    S.step()
+    torch.cuda.synchronize()
+    return models, layouts, S
+
+
+def test_batched_layouts_every_system(api, batched):
+    models, layouts, S = batched
+    assert S.n_systems == 384
+    for s in range(S.n_systems):
+        X, Y, info, finfo = S.system(s)
+        rep = S.reports[s]
+        assert int(info) == 0 and int(finfo) == 0, s
+        assert rep["converged"] and rep["iters"] <= 3, (s, rep)
+        na = Y.shape[0]
+        n = X.shape[0]
+        Zp, Xp, Yp = S.padded(s)
+        gi, k = S.where[s]
+        B = S.groups[gi].B[k, :n, :na]
+        Z = Zp[:n, :n]
+        R = B - Z @ X
+        rel = (torch.linalg.norm(R) / (torch.linalg.norm(Z) * torch.linalg.norm(X))).item()
+        assert rel <= 1.001e-10, (s, rel)
+        assert torch.linalg.norm(Y - Y.T).item() <= 1e-8 * torch.linalg.norm(Y).item()
+        assert not Xp[n:].any() and not Xp[:, na:].any()
+        assert not Yp[na:].any() and not Yp[:, na:].any()
+
+
+def test_batched_layouts_sampled_against_oracle(api, batched):
+    models, layouts, S = batched
+    sizes = np.array(S.n_ant)
+    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
+    rng = np.random.default_rng(384)
+    for s in picks:
+        li, f = S.layout_of[s]
+        x, y, _ = layouts[li]
+        m = models[f]
+        na = x.size
+        X, Y, _, _ = S.system(s)
+        Zo = oracle_fill_chunked(m, x, y)
+        Zp = S.padded(s)[0].cpu().numpy()
+        eps, zero_ok, _ = block_eps(Zp[:na * m.n_mbf, :na * m.n_mbf], Zo, m.n_mbf)
+        assert eps <= 1e-12 and zero_ok, (s, eps)
+        ports = rng.choice(na, min(na, 6), replace=False)
+        Bo = osolve.port_rhs(m.w, na)[:, ports]
+        Xo = np.linalg.solve(Zo, Bo)
+        assert _port_rel(X.cpu().numpy()[:, ports], Xo) <= 1e-6, s
+        Yo = osolve.admittance(Xo, m.w, na)
+        assert _rel(Y.cpu().numpy()[:, ports], Yo) <= 1e-6, s

@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import fill as ofill, solve as osolve  # noqa: E402
 
-from parity import oracle_models, pack  # noqa: E402
+from parity import oracle_fill_chunked, oracle_models, pack  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -19,23 +19,6 @@ pytestmark = pytest.mark.gpu
 def api():
     from paper_1702_03781_amd import api as A
     return A
-
-
-def _oracle_fill_within(model, x, y, ri):
-    """The oracle fill with the blocks beyond the radius of influence left at
-    zero without evaluating them (same numbers as oracle.fill(..., ri))."""
-    na, nm = x.size, model.n_mbf
-    Z = np.zeros((na, nm, na, nm), dtype=np.complex128)
-    mm, nn = np.meshgrid(np.arange(na), np.arange(na), indexing="ij")
-    d = np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :])
-    sel = (mm != nn) & (d <= ri)
-    Rx, Ry = (x[:, None] - x[None, :])[sel], (y[:, None] - y[None, :])[sel]
-    blocks = np.concatenate([ofill.eval_model(model, Rx[i:i + 32768], Ry[i:i + 32768])
-                             for i in range(0, Rx.size, 32768)])
-    Z[mm[sel], :, nn[sel], :] = blocks
-    for m in range(na):
-        Z[m, :, m, :] = model.Z_self
-    return Z.reshape(na * nm, na * nm)
 
 
 @pytest.fixture(scope="module")
@@ -91,7 +74,7 @@ def test_large_solve_refined(api, large):
     Yh = Y[0].cpu().numpy()
     assert np.linalg.norm(Yh - Yh.T) <= 1e-8 * np.linalg.norm(Yh)
     ports = np.random.default_rng(1024).choice(wl.n_ant, 6, replace=False)
-    Zo = _oracle_fill_within(m, wl.x, wl.y, wl.ri)
+    Zo = oracle_fill_chunked(m, wl.x, wl.y, wl.ri)
     Bo = osolve.port_rhs(m.w, wl.n_ant)[:, ports]
     Xo = np.linalg.solve(Zo, Bo)
     Xg = X[0].cpu().numpy()[:, ports]
