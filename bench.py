@@ -238,6 +238,72 @@ def bench_batched(args, api, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_tessellated(args, api, torch, dev):
+    """The 1024-element array (38 m disk, 8 MBFs, 200 MHz) by the overlapping-
+    subarray tessellation (every cell's subarray one system of a batch, inner
+    ports only) against the full refined solve of the whole array (n = 8192,
+    1024 ports); EEP error of the tessellation over 128 directions."""
+    import numpy as np
+
+    from workloads import directions, workload
+
+    wl = workload("cfg5")
+    samples = api.to_device_samples(wl.elem.samples, dev)
+    model = api.harp_fit(samples, wl.elem.wire_radius, wl.freqs[0], wl.P[0], wl.Q, wl.r_min)
+    mb = api.stack_models([model])
+    th, ph = directions(128, seed=9)
+    tht, pht = torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)
+    x, y = torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev)
+    T = api.TessellatedSolver(mb, wl.x, wl.y, [0], args.r_in, args.r_ext, tol=args.tol, streams=args.streams)
+    full = api.StationSolver(mb, x, y, "refined", tol=args.tol)
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ms_t = timed(T.step)
+    ms_f = timed(full.step)
+    E = T.patterns([model], 0, tht, pht)
+    Ef = api.embedded_patterns(model, x, y, full.X, tht, pht)
+    err = ((E - Ef).abs().pow(2).sum(dim=(1, 2)).sqrt() / Ef.abs().pow(2).sum(dim=(1, 2)).sqrt()).cpu().numpy()
+    conv = all(r["converged"] for r in T.batch.reports) and all(r["converged"] for r in full.reports)
+    sizes = [len(c.members) for c in T.cells]
+    out = {
+        "metric": "reduced-Z entries/s + port solves/s at rel err 1e-6 vs FP64 plain path",
+        "value": wl.n_ant / (ms_t * 1e-3),
+        "unit": "port solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_t,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("tessellated large array: 1024 elements (38 m disk, 1.5 m min spacing), 8 MBFs x 64 "
+                         "dipole samples, 200 MHz; hexagonal cells R_in = %g m, extension R_ext = %g m, every "
+                         "subarray one system of a batch with its inner ports excited; complex64 LU + FP64 "
+                         "refinement" % (args.r_in, args.r_ext)),
+            "cells": len(T.cells), "subarray_sizes": [min(sizes), max(sizes), float(np.mean(sizes))],
+            "groups": [(len(g.members), g.n) for g in T.batch.groups], "refine_tol": args.tol,
+        },
+        "full_solve_ms": ms_f,
+        "speedup_over_full_solve": ms_f / ms_t,
+        "eep_rel_err_vs_full": {"mean": float(err.mean()), "max": float(err.max()), "directions": 128},
+        "all_converged": conv,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,9 +313,12 @@ def main():
     ap.add_argument("--cpu-freqs", type=int, default=8,
                     help="frequencies in the CPU-baseline sample (0: skip)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
-    ap.add_argument("--workload", choices=["station", "batched"], default="station",
+    ap.add_argument("--workload", choices=["station", "batched", "tessellated"], default="station",
                     help="station: the 16-frequency station sweep (default); batched: 48 unequal "
-                         "layouts x 8 frequencies")
+                         "layouts x 8 frequencies; tessellated: the 1024-element array by overlapping "
+                         "subarrays against its full solve")
+    ap.add_argument("--r-in", type=float, default=6.0, help="tessellation inner radius (m)")
+    ap.add_argument("--r-ext", type=float, default=6.0, help="tessellation extension (m)")
     ap.add_argument("--streams", type=int, default=2, help="HIP streams of the batched workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference kernel that "
@@ -284,6 +353,8 @@ def main():
         return
     if args.workload == "batched":
         return bench_batched(args, api, torch, dev)
+    if args.workload == "tessellated":
+        return bench_tessellated(args, api, torch, dev)
     wl = workload("cfg2")
     n, na, nf = wl.n, wl.n_ant, len(wl.freqs)
 

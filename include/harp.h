@@ -141,11 +141,14 @@ harp_status harp_fill(const void *d_models, int64_t model_stride, int32_t n_freq
 /* ------------------------------------------------------------------------ */
 
 /* One system of a batch: the layout of n_ant antennas whose positions are
- * x[pos .. pos + n_ant), y[same), evaluated with model blob number `model`. */
+ * x[pos .. pos + n_ant), y[same), evaluated with model blob number `model`;
+ * its ports are its first n_ports antennas (0: all n_ant). */
 typedef struct {
     int32_t model;
     int32_t n_ant;
     int64_t pos;
+    int32_t n_ports;
+    int32_t reserved;  /* 0 */
 } harp_system;
 
 /* Grouping plan (host only, no device work).  The n_sys systems (antenna
@@ -180,22 +183,44 @@ harp_status harp_fill_systems(const void *d_models, int64_t model_stride, int32_
                               int64_t ldz, int64_t stride_z, void *d_Z32, int64_t ld32,
                               int64_t stride32, int32_t *d_info, hipStream_t stream);
 
-/* harp_port_rhs for a padded group: B_s (complex128, N x n_ant_pad) holds the
- * unit excitation of the system's ports (its model's weights) in its leading
- * n x n_ant block and zeros elsewhere (a descriptor out of range gives zeros). */
+/* harp_port_rhs for a padded group: B_s (complex128, N x n_ports_pad) holds
+ * the unit excitation of the system's ports (its model's weights) in its
+ * leading n x n_ports block (column j: e_j (x) w) and zeros elsewhere.  A
+ * descriptor out of range, or with n_ports beyond n_ant or n_ports_pad, gives
+ * zeros. */
 harp_status harp_port_rhs_systems(const void *d_models, int64_t model_stride, int32_t n_models,
                                   int32_t n_mbf, const harp_system *d_sys, int32_t n_sys,
-                                  int32_t n_ant_pad, void *d_B, int64_t ldb, int64_t stride_b,
-                                  hipStream_t stream);
+                                  int32_t n_ant_pad, int32_t n_ports_pad, void *d_B, int64_t ldb,
+                                  int64_t stride_b, hipStream_t stream);
 
 /* harp_port_admittance for a padded group: Y_s (complex128,
- * n_ant_pad x n_ant_pad) = W^T X in its leading n_ant x n_ant block, zeros
- * elsewhere. */
+ * n_ant_pad x n_ports_pad) = W^T X_s (X_s: N x n_ports_pad) in its leading
+ * n_ant x n_ports block (the currents at every port of the system for a unit
+ * voltage at each of its excited ports), zeros elsewhere. */
 harp_status harp_port_admittance_systems(const void *d_models, int64_t model_stride, int32_t n_models,
                                          int32_t n_mbf, const harp_system *d_sys, int32_t n_sys,
-                                         int32_t n_ant_pad, const void *d_X, int64_t ldx,
-                                         int64_t stride_x, void *d_Y, int64_t ldy, int64_t stride_y,
-                                         hipStream_t stream);
+                                         int32_t n_ant_pad, int32_t n_ports_pad, const void *d_X,
+                                         int64_t ldx, int64_t stride_x, void *d_Y, int64_t ldy,
+                                         int64_t stride_y, hipStream_t stream);
+
+/* Overlapping-subarray tessellation (Section II-D; host only, no device
+ * work).  Flat-top regular hexagonal cells of circumradius r_in with centres
+ * (ox + 1.5 r_in i, oy + sqrt(3) r_in (j + i / 2)), i, j integers, tile the
+ * plane; each antenna (x[], y[], host, n_ant) belongs to the inner part of
+ * the cell whose centre is nearest (ties: smallest (i, j)).  The subarray of a
+ * cell is every antenna inside the concentric flat-top hexagon of
+ * circumradius r_in + r_ext.  Only cells with at least one inner antenna are
+ * returned, in (i, j) order.  Outputs (host, caller-owned): *n_cells,
+ * *n_members; and when members != NULL: cell_begin[n_cells + 1] (offsets into
+ * members), cell_inner[n_cells] (inner antennas of the cell, listed first in
+ * ascending order, followed by the cell's other antennas in ascending order),
+ * members[n_members], centers[2 n_cells] (x, y).  Call once with
+ * members == NULL for the sizes.  HARP_E_ARG on r_in <= 0, r_ext < 0 or
+ * non-finite input.  Cost O(n_ant x cells). */
+harp_status harp_tessellate(const double *x, const double *y, int32_t n_ant, double r_in, double r_ext,
+                            double ox, double oy, int32_t *n_cells, int64_t *n_members,
+                            int64_t *cell_begin, int32_t *cell_inner, int32_t *members,
+                            double *centers);
 
 /* ------------------------------------------------------------------------ */
 /* Ports (Sections I and II-C)                                               */

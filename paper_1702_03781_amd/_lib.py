@@ -21,6 +21,7 @@ c_vp = ctypes.c_void_p
 c_szp = ctypes.POINTER(ctypes.c_size_t)
 c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_dblp = ctypes.POINTER(ctypes.c_double)
+c_i64p = ctypes.POINTER(ctypes.c_int64)
 
 
 class HarpElement(ctypes.Structure):
@@ -50,10 +51,12 @@ SIGNATURES = {
                                 c_i32p, c_i32p]),
     "harp_fill_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_i64, c_vp, c_i32,
                                   c_i32, c_dbl, c_i32, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]),
-    "harp_port_rhs_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64, c_i64,
-                                      c_vp]),
-    "harp_port_admittance_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_vp, c_i64,
-                                             c_i64, c_vp, c_i64, c_i64, c_vp]),
+    "harp_port_rhs_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_i64,
+                                      c_i64, c_vp]),
+    "harp_port_admittance_systems": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp,
+                                             c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
+    "harp_tessellate": (c_i32, [c_dblp, c_dblp, c_i32, c_dbl, c_dbl, c_dbl, c_dbl, c_i32p, c_i64p, c_i64p,
+                                c_i32p, c_i32p, c_dblp]),
     "harp_port_rhs": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp]),
     "harp_port_admittance": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp,
                                      c_i64, c_i64, c_vp]),

@@ -507,7 +507,8 @@ __all__ = [
     "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
     "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
     "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "harp_fill_systems", "harp_port_rhs_systems",
-    "harp_port_admittance_systems", "BatchSolver", "StationSolver",
+    "harp_port_admittance_systems", "BatchSolver", "StationSolver", "Cell", "harp_tessellate",
+    "TessellatedSolver",
 ]
 
 
@@ -591,13 +592,17 @@ class StationSolver:
 # batches of unequal layouts
 # --------------------------------------------------------------------------
 
-SYSTEM_DTYPE = np.dtype([("model", "<i4"), ("n_ant", "<i4"), ("pos", "<i8")])   # harp_system
+SYSTEM_DTYPE = np.dtype([("model", "<i4"), ("n_ant", "<i4"), ("pos", "<i8"), ("n_ports", "<i4"),
+                         ("reserved", "<i4")])   # harp_system
 
 
-def systems_tensor(model_idx, n_ant, pos, device="cuda") -> torch.Tensor:
-    """Device array of harp_system descriptors (16 bytes each)."""
+def systems_tensor(model_idx, n_ant, pos, device="cuda", n_ports=None) -> torch.Tensor:
+    """Device array of harp_system descriptors (24 bytes each); n_ports None
+    or 0: every antenna of a system is a port."""
     a = np.zeros(len(model_idx), dtype=SYSTEM_DTYPE)
     a["model"], a["n_ant"], a["pos"] = model_idx, n_ant, pos
+    if n_ports is not None:
+        a["n_ports"] = n_ports
     return torch.from_numpy(a.view(np.uint8).copy()).to(device)
 
 
@@ -642,29 +647,33 @@ def harp_fill_systems(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, sys:
 
 
 def harp_port_rhs_systems(models: ModelBatch, sys: torch.Tensor, n_ant_pad: int,
-                          B: torch.Tensor | None = None):
+                          n_ports_pad: int | None = None, B: torch.Tensor | None = None):
     dev = models.data.device
     n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
     n = n_ant_pad * models.n_mbf
+    n_ports_pad = n_ant_pad if n_ports_pad is None else n_ports_pad
     if B is None:
-        B = colmajor(n_sys, n, n_ant_pad, torch.complex128, dev)
+        B = colmajor(n_sys, n, n_ports_pad, torch.complex128, dev)
     pb, ldb, sb = _cm(B, "B")
     check(lib().harp_port_rhs_systems(_ptr(models.data), models.stride, models.n_freq, models.n_mbf, _ptr(sys),
-                                      n_sys, n_ant_pad, pb, ldb, sb, _stream(dev)), "harp_port_rhs_systems")
+                                      n_sys, n_ant_pad, n_ports_pad, pb, ldb, sb, _stream(dev)),
+          "harp_port_rhs_systems")
     return B
 
 
 def harp_port_admittance_systems(models: ModelBatch, sys: torch.Tensor, X: torch.Tensor,
                                  Y: torch.Tensor | None = None):
+    """Y_s = W^T X_s (n_ant_pad x n_ports_pad) for X (n_sys, N, n_ports_pad)."""
     dev = models.data.device
     n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
-    n_ant_pad = X.shape[-1]
+    n_ant_pad = X.shape[-2] // models.n_mbf
+    n_ports_pad = X.shape[-1]
     if Y is None:
-        Y = colmajor(n_sys, n_ant_pad, n_ant_pad, torch.complex128, dev)
+        Y = colmajor(n_sys, n_ant_pad, n_ports_pad, torch.complex128, dev)
     px, ldx, sx = _cm(X, "X")
     py, ldy, sy = _cm(Y, "Y")
     check(lib().harp_port_admittance_systems(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
-                                             _ptr(sys), n_sys, n_ant_pad, px, ldx, sx, py, ldy, sy,
+                                             _ptr(sys), n_sys, n_ant_pad, n_ports_pad, px, ldx, sx, py, ldy, sy,
                                              _stream(dev)), "harp_port_admittance_systems")
     return Y
 
@@ -672,24 +681,27 @@ def harp_port_admittance_systems(models: ModelBatch, sys: torch.Tensor, X: torch
 class _Group:
     """Device buffers of one padded group (refined path)."""
 
-    def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, dev):
+    def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, n_ports, pad_multiple, dev):
         self.members, self.n_pad = members, n_pad
         c = len(members)
         n = self.n = n_pad * models.n_mbf
+        npmax = max(n_ports[i] for i in members)
+        self.n_ports_pad = min(n_pad, -(-npmax // pad_multiple) * pad_multiple)
         self.sys = systems_tensor([model_idx[i] for i in members], [n_ant[i] for i in members],
-                                  [pos[i] for i in members], dev)
+                                  [pos[i] for i in members], dev, n_ports=[n_ports[i] for i in members])
+        npp = self.n_ports_pad
         self.Z64 = colmajor(c, n, n, torch.complex128, dev)
         self.Z32 = colmajor(c, n, n, torch.complex64, dev)
-        self.B = colmajor(c, n, n_pad, torch.complex128, dev)
-        self.X = colmajor(c, n, n_pad, torch.complex128, dev)
-        self.Y = colmajor(c, n_pad, n_pad, torch.complex128, dev)
+        self.B = colmajor(c, n, npp, torch.complex128, dev)
+        self.X = colmajor(c, n, npp, torch.complex128, dev)
+        self.Y = colmajor(c, n_pad, npp, torch.complex128, dev)
         self.info = torch.empty(c, dtype=torch.int32, device=dev)
         self.finfo = torch.empty(c, dtype=torch.int32, device=dev)
         self.ipiv = torch.empty((c, n), dtype=torch.int32, device=dev)
         b = ctypes.c_size_t()
         check(lib().reduced_factor_ws(n, c, C64, ctypes.byref(b)), "reduced_factor_ws")
         self.aux, self.aux_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
-        check(lib().reduced_solve_ws(n, n_pad, c, C64, 1, ctypes.byref(b)), "reduced_solve_ws")
+        check(lib().reduced_solve_ws(n, npp, c, C64, 1, ctypes.byref(b)), "reduced_solve_ws")
         self.ws, self.ws_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
 
 
@@ -697,30 +709,39 @@ class BatchSolver:
     """The refined hot path (FP64 fill written as complex128 and complex64,
     complex64 LU, solve, FP64 refinement, admittances) for a batch of
     unequal layouts, each at several frequencies, reusing one model per
-    frequency.  Systems are grouped by harp_batch_plan and padded per group;
-    groups are issued round-robin on `streams` HIP streams (default
-    priority), all buffers allocated once."""
+    frequency.  A layout is (x, y, frequency indices) or (x, y, frequency
+    indices, n_ports): its ports are its first n_ports antennas (default all).
+    Systems are grouped by harp_batch_plan and padded per group; groups are
+    issued round-robin on `streams` HIP streams (default priority), all
+    buffers allocated once."""
 
     def __init__(self, models: ModelBatch, layouts, tol: float = 1e-10, max_iter: int = 10,
                  streams: int = 1, ri: float = 0.0, **plan_kw):
         dev = models.data.device
         self.models, self.tol, self.max_iter, self.ri = models, tol, max_iter, ri
-        xs, ys, model_idx, n_ant, pos, self.layout_of = [], [], [], [], [], []
+        xs, ys, model_idx, n_ant, pos, n_ports, self.layout_of = [], [], [], [], [], [], []
         off = 0
-        for li, (x, y, fidx) in enumerate(layouts):
+        for li, lay in enumerate(layouts):
+            x, y, fidx = lay[0], lay[1], lay[2]
             xs.append(np.asarray(x, dtype=np.float64))
             ys.append(np.asarray(y, dtype=np.float64))
+            npt = int(lay[3]) if len(lay) > 3 else int(xs[-1].size)
+            if not 0 < npt <= xs[-1].size:
+                raise ValueError(f"layout {li}: n_ports {npt} not in [1, {xs[-1].size}]")
             for f in fidx:
                 model_idx.append(int(f))
                 n_ant.append(int(xs[-1].size))
+                n_ports.append(npt)
                 pos.append(off)
                 self.layout_of.append((li, int(f)))
             off += xs[-1].size
         self.x = torch.from_numpy(np.concatenate(xs)).to(dev)
         self.y = torch.from_numpy(np.concatenate(ys)).to(dev)
-        self.n_ant = n_ant
+        self.n_ant, self.n_ports = n_ant, n_ports
         order, groups = harp_batch_plan(n_ant, models.n_mbf, **plan_kw)
-        self.groups = [_Group(models, order[b:e], pad, model_idx, n_ant, pos, dev) for b, e, pad in groups]
+        pm = plan_kw.get("pad_multiple", 8)
+        self.groups = [_Group(models, order[b:e], pad, model_idx, n_ant, pos, n_ports, pm, dev)
+                       for b, e, pad in groups]
         self.where = {}
         for gi, g in enumerate(self.groups):
             for k, s in enumerate(g.members):
@@ -742,7 +763,7 @@ class BatchSolver:
                                   C128, pz, ldz, sz, p32, ld32, s32, _ptr(g.info), st), "harp_fill_systems")
         pb, ldb, sb = _cm(g.B, "B")
         check(L.harp_port_rhs_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c, g.n_pad,
-                                      pb, ldb, sb, st), "harp_port_rhs_systems")
+                                      g.n_ports_pad, pb, ldb, sb, st), "harp_port_rhs_systems")
         check(L.reduced_factor(g.n, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.finfo), _ptr(g.aux),
                                g.aux_bytes, st), "reduced_factor")
 
@@ -755,12 +776,12 @@ class BatchSolver:
         px, ldx, sx = _cm(g.X, "X")
         ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter))
         rep = (HarpRefineReport * c)()
-        check(L.reduced_solve(g.n, g.n_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux), g.aux_bytes,
+        check(L.reduced_solve(g.n, g.n_ports_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux), g.aux_bytes,
                               pb, ldb, sb, px, ldx, sx, ctypes.byref(ref), rep, _ptr(g.ws), g.ws_bytes, st),
               "reduced_solve")
         py, ldy, sy = _cm(g.Y, "Y")
         check(L.harp_port_admittance_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c,
-                                             g.n_pad, px, ldx, sx, py, ldy, sy, st),
+                                             g.n_pad, g.n_ports_pad, px, ldx, sx, py, ldy, sy, st),
               "harp_port_admittance_systems")
         return rep
 
@@ -789,18 +810,102 @@ class BatchSolver:
         self.reports = reports
 
     def system(self, s: int):
-        """(X, Y, fill info, factor info) of system s, unpadded views."""
+        """(X, Y, fill info, factor info) of system s, unpadded views: X is
+        n x n_ports, Y is n_ant x n_ports."""
         gi, k = self.where[s]
         g = self.groups[gi]
-        na = self.n_ant[s]
+        na, npt = self.n_ant[s], self.n_ports[s]
         n = na * self.models.n_mbf
-        return g.X[k, :n, :na], g.Y[k, :na, :na], g.info[k], g.finfo[k]
+        return g.X[k, :n, :npt], g.Y[k, :na, :npt], g.info[k], g.finfo[k]
 
     def padded(self, s: int):
         """(Z64, X, Y) of system s with its padding."""
         gi, k = self.where[s]
         g = self.groups[gi]
         return g.Z64[k], g.X[k], g.Y[k]
+
+
+@dataclass
+class Cell:
+    """One cell of the overlapping-subarray tessellation."""
+    center: tuple
+    members: np.ndarray     # antenna indices, inner ones first
+    n_inner: int
+
+
+def harp_tessellate(x, y, r_in: float, r_ext: float, origin=(0.0, 0.0)):
+    """Cells of the hexagonal overlapping-subarray tessellation (Section II-D)
+    of the layout (x, y) (host arrays), see include/harp.h."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n = int(x.size)
+    dp = ctypes.POINTER(ctypes.c_double)
+    nc, nm = ctypes.c_int32(), ctypes.c_int64()
+    args = (x.ctypes.data_as(dp), y.ctypes.data_as(dp), n, float(r_in), float(r_ext), float(origin[0]),
+            float(origin[1]), ctypes.byref(nc), ctypes.byref(nm))
+    check(lib().harp_tessellate(*args, None, None, None, None), "harp_tessellate")
+    begin = np.zeros(nc.value + 1, dtype=np.int64)
+    inner = np.zeros(nc.value, dtype=np.int32)
+    members = np.zeros(max(1, nm.value), dtype=np.int32)
+    centers = np.zeros(2 * nc.value, dtype=np.float64)
+    check(lib().harp_tessellate(*args, begin.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                inner.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                members.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                centers.ctypes.data_as(dp)), "harp_tessellate")
+    return [Cell((float(centers[2 * c]), float(centers[2 * c + 1])), members[begin[c]:begin[c + 1]].copy(),
+                 int(inner[c])) for c in range(nc.value)]
+
+
+class TessellatedSolver:
+    """The tessellation approach of Section II-D on the batch path: every
+    cell's subarray (its antennas within the outer hexagon, the cell's own
+    antennas first) is one system at each frequency, with only the cell's own
+    antennas' ports excited; antenna a's solution is taken from its own cell's
+    subarray (currents on the subarray's antennas, zero elsewhere)."""
+
+    def __init__(self, models: ModelBatch, x, y, fidx, r_in: float, r_ext: float, origin=(0.0, 0.0),
+                 tol: float = 1e-10, max_iter: int = 10, streams: int = 2, **plan_kw):
+        self.x = np.ascontiguousarray(x, dtype=np.float64)
+        self.y = np.ascontiguousarray(y, dtype=np.float64)
+        self.fidx = [int(f) for f in fidx]
+        self.cells = harp_tessellate(self.x, self.y, r_in, r_ext, origin)
+        layouts = [(self.x[c.members], self.y[c.members], self.fidx, c.n_inner) for c in self.cells]
+        self.batch = BatchSolver(models, layouts, tol=tol, max_iter=max_iter, streams=streams, **plan_kw)
+        self.models = models
+        self.cell_of = np.empty(self.x.size, dtype=np.int64)
+        self.local = np.empty(self.x.size, dtype=np.int64)
+        for ci, c in enumerate(self.cells):
+            self.cell_of[c.members[:c.n_inner]] = ci
+            self.local[c.members[:c.n_inner]] = np.arange(c.n_inner)
+
+    def step(self):
+        self.batch.step()
+
+    def system(self, cell: int, f: int) -> int:
+        """Batch system index of (cell, model index f)."""
+        return cell * len(self.fidx) + self.fidx.index(int(f))
+
+    def port(self, a: int, f: int):
+        """(subarray antenna indices, X column (n_sub N_m), Y column (n_sub))
+        of a unit voltage at port a at model index f."""
+        ci = int(self.cell_of[a])
+        X, Y, _, _ = self.batch.system(self.system(ci, f))
+        j = int(self.local[a])
+        return self.cells[ci].members, X[:, j], Y[:, j]
+
+    def patterns(self, models_list, f: int, theta: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:
+        """Embedded element patterns E[a, dir, (theta, phi)] of every antenna at
+        model index f (Eqs. 5-6 over its subarray's currents); models_list[f]
+        is the Model of that frequency."""
+        dev = theta.device
+        E = torch.empty((self.x.size, int(theta.numel()), 2), dtype=torch.complex128, device=dev)
+        for ci, c in enumerate(self.cells):
+            X, _, _, _ = self.batch.system(self.system(ci, f))
+            xs = torch.from_numpy(self.x[c.members]).to(dev)
+            ys = torch.from_numpy(self.y[c.members]).to(dev)
+            Ec = embedded_patterns(models_list[f], xs, ys, X, theta, phi)
+            E[torch.from_numpy(c.members[:c.n_inner]).to(dev)] = Ec
+        return E
 
 
 def prof_enable(on: bool) -> None:

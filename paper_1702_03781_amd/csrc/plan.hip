@@ -12,9 +12,11 @@
 // to minimise the modelled time
 //   sum over groups of  t_group + t_order * N + t_system * c * N^3
 // (c systems of padded order N per group).
+#include <math.h>
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <numeric>
 #include <vector>
 
@@ -71,5 +73,106 @@ extern "C" harp_status harp_batch_plan(const int32_t* n_ant, int32_t n_sys, int3
     group_begin[g] = n_sys;
     *n_groups = g;
     std::copy(idx.begin(), idx.end(), order);
+    return HARP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Overlapping-subarray tessellation (Section II-D, subarray figure).
+//
+// Flat-top regular hexagons of circumradius R tile the plane with centres on
+// the lattice c(i, j) = o + (1.5 R i, sqrt(3) R (j + i / 2)); the hexagon of a
+// centre is exactly the set of points nearer to it than to any other centre,
+// so an antenna's inner cell is its nearest centre.  A point d from a centre
+// lies in the concentric flat-top hexagon of circumradius Rh iff
+//   max(2 |d_y| / sqrt(3), |d_x| + |d_y| / sqrt(3)) <= Rh.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr double kSqrt3 = 1.73205080756887729353;
+
+inline double hex_radius(double dx, double dy) {
+    const double ay = std::fabs(dy) / kSqrt3;
+    return std::max(2.0 * ay, std::fabs(dx) + ay);
+}
+
+struct Cell {
+    int64_t i, j;
+    bool operator<(const Cell& o) const { return i != o.i ? i < o.i : j < o.j; }
+    bool operator==(const Cell& o) const { return i == o.i && j == o.j; }
+};
+
+}  // namespace
+
+extern "C" harp_status harp_tessellate(const double* x, const double* y, int32_t n_ant, double r_in, double r_ext,
+                                       double ox, double oy, int32_t* n_cells, int64_t* n_members,
+                                       int64_t* cell_begin, int32_t* cell_inner, int32_t* members,
+                                       double* centers) {
+    if (!x || !y || !n_cells || !n_members || n_ant <= 0) return HARP_E_ARG;
+    if (!(r_in > 0.0) || !(r_ext >= 0.0) || !std::isfinite(r_in) || !std::isfinite(r_ext) || !std::isfinite(ox) ||
+        !std::isfinite(oy))
+        return HARP_E_ARG;
+    const double R = r_in, Rout = r_in + r_ext;
+    auto centre = [&](const Cell& c, double* cx, double* cy) {
+        *cx = ox + 1.5 * R * double(c.i);
+        *cy = oy + kSqrt3 * R * (double(c.j) + 0.5 * double(c.i));
+    };
+    // inner cell of every antenna: the nearest centre among the lattice points
+    // around the fractional lattice coordinates (ties: smallest (i, j))
+    std::vector<Cell> own(n_ant);
+    for (int a = 0; a < n_ant; ++a) {
+        if (!std::isfinite(x[a]) || !std::isfinite(y[a])) return HARP_E_ARG;
+        const double fi = (x[a] - ox) / (1.5 * R);
+        const double fj = (y[a] - oy) / (kSqrt3 * R) - 0.5 * fi;
+        const int64_t i0 = int64_t(std::floor(fi)), j0 = int64_t(std::floor(fj));
+        Cell best{0, 0};
+        double bd = -1.0;
+        for (int64_t i = i0 - 1; i <= i0 + 2; ++i) {
+            for (int64_t j = j0 - 2; j <= j0 + 2; ++j) {
+                double cx, cy;
+                centre(Cell{i, j}, &cx, &cy);
+                const double d = (x[a] - cx) * (x[a] - cx) + (y[a] - cy) * (y[a] - cy);
+                if (bd < 0.0 || d < bd || (d == bd && Cell{i, j} < best)) {
+                    bd = d;
+                    best = Cell{i, j};
+                }
+            }
+        }
+        own[a] = best;
+    }
+    std::vector<Cell> cells(own);
+    std::sort(cells.begin(), cells.end());
+    cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+    const int nc = int(cells.size());
+    // subarray of each cell: its inner antennas (ascending), then every other
+    // antenna inside the outer hexagon (ascending)
+    int64_t total = 0;
+    std::vector<int32_t> list;
+    std::vector<int64_t> begin(size_t(nc) + 1, 0);
+    std::vector<int32_t> inner(nc, 0);
+    const bool write = members != nullptr;
+    if (write && (!cell_begin || !cell_inner || !centers)) return HARP_E_ARG;
+    for (int c = 0; c < nc; ++c) {
+        double cx, cy;
+        centre(cells[c], &cx, &cy);
+        begin[c] = total;
+        list.clear();
+        for (int a = 0; a < n_ant; ++a)
+            if (own[a] == cells[c]) list.push_back(a);
+        inner[c] = int32_t(list.size());
+        for (int a = 0; a < n_ant; ++a)
+            if (!(own[a] == cells[c]) && hex_radius(x[a] - cx, y[a] - cy) <= Rout) list.push_back(a);
+        if (write) {
+            std::copy(list.begin(), list.end(), members + total);
+            cell_inner[c] = inner[c];
+            centers[2 * c] = cx;
+            centers[2 * c + 1] = cy;
+        }
+        total += int64_t(list.size());
+    }
+    begin[nc] = total;
+    if (write) std::copy(begin.begin(), begin.end(), cell_begin);
+    *n_cells = nc;
+    *n_members = total;
     return HARP_OK;
 }

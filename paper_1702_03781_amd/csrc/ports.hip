@@ -10,66 +10,72 @@
 namespace harp {
 namespace {
 
-// The system behind matrix f: its model and antenna count (all n_ant
-// antennas and model f without descriptors).  False for a descriptor out of
-// range: its matrix is then written as zeros.
-__device__ inline bool system_of(const harp_system* sys, int n_models, int f, int n_ant, int* model, int* ns) {
+// The system behind matrix f: its model, antenna count and port count (all
+// n_ant antennas, model f and n_cols ports without descriptors).  False for a
+// descriptor out of range: its matrices are then written as zeros.
+__device__ inline bool system_of(const harp_system* sys, int n_models, int f, int n_ant, int n_cols, int* model,
+                                 int* ns, int* np) {
     *model = f;
     *ns = n_ant;
+    *np = n_cols;
     if (!sys) return true;
     const harp_system d = sys[f];
-    if (d.model < 0 || d.model >= n_models || d.n_ant < 1 || d.n_ant > n_ant) return false;
+    const int ports = d.n_ports == 0 ? d.n_ant : d.n_ports;
+    if (d.model < 0 || d.model >= n_models || d.n_ant < 1 || d.n_ant > n_ant || ports < 0 || ports > d.n_ant ||
+        ports > n_cols)
+        return false;
     *model = d.model;
     *ns = d.n_ant;
+    *np = ports;
     return true;
 }
 
-// B (complex128, n x n_ant per matrix): one thread per entry.  Rows and
-// columns of padding antennas (beyond the system's own) are zero.
+// B (complex128, n x n_cols per matrix, n = n_ant n_mbf): one thread per
+// entry; column j < ports is e_j (x) w, the rest (and the rows of padding
+// antennas) zero.
 __global__ void __launch_bounds__(256)
-    port_rhs_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf, int n_ant,
+    port_rhs_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf, int n_ant, int n_cols,
                     double2* __restrict__ B, int64_t ldb, int64_t stride_b, const harp_system* __restrict__ sys,
                     int n_models) {
     const int f = blockIdx.y;
-    int mi, ns;
-    const bool ok = system_of(sys, n_models, f, n_ant, &mi, &ns);
+    int mi, ns, np;
+    const bool ok = system_of(sys, n_models, f, n_ant, n_cols, &mi, &ns, &np);
     const char* model = models + size_t(ok ? mi : 0) * model_stride;
     const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
     const double2* w = reinterpret_cast<const double2*>(model + h->off_port);
     const int64_t n = int64_t(n_ant) * n_mbf;
-    const int64_t total = n * n_ant;
+    const int64_t total = n * n_cols;
     double2* Bf = B + size_t(f) * stride_b;
     for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += int64_t(gridDim.x) * blockDim.x) {
         const int64_t col = e / n, row = e % n;
         const int64_t ant = row / n_mbf, T = row % n_mbf;
         double2 v = {0.0, 0.0};
-        if (ok && ant == col && ant < ns) v = w[T];
+        if (ok && ant == col && col < np) v = w[T];
         Bf[col * ldb + row] = v;
     }
 }
 
-// Y (complex128, n_ant x n_ant per matrix): one thread per entry; entries of
-// padding antennas are zero.
+// Y (complex128, n_ant x n_cols per matrix): Y_ij = sum_T w_T X[i N_m + T, j]
+// for antennas i < ns and ports j < np, zero elsewhere; one thread per entry.
 __global__ void __launch_bounds__(256)
-    port_admittance_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf,
-                           int n_ant, const double2* __restrict__ X, int64_t ldx, int64_t stride_x,
-                           double2* __restrict__ Y, int64_t ldy, int64_t stride_y,
-                           const harp_system* __restrict__ sys, int n_models) {
+    port_admittance_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf, int n_ant, int n_cols,
+                           const double2* __restrict__ X, int64_t ldx, int64_t stride_x, double2* __restrict__ Y,
+                           int64_t ldy, int64_t stride_y, const harp_system* __restrict__ sys, int n_models) {
     const int f = blockIdx.y;
-    int mi, ns;
-    const bool ok = system_of(sys, n_models, f, n_ant, &mi, &ns);
+    int mi, ns, np;
+    const bool ok = system_of(sys, n_models, f, n_ant, n_cols, &mi, &ns, &np);
     const char* model = models + size_t(ok ? mi : 0) * model_stride;
     const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
     const double2* w = reinterpret_cast<const double2*>(model + h->off_port);
-    const int64_t total = int64_t(n_ant) * n_ant;
+    const int64_t total = int64_t(n_ant) * n_cols;
     const double2* Xf = X + size_t(f) * stride_x;
     double2* Yf = Y + size_t(f) * stride_y;
     for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
          e += int64_t(gridDim.x) * blockDim.x) {
         const int64_t j = e / n_ant, i = e % n_ant;
         double re = 0.0, im = 0.0;
-        if (ok && i < ns && j < ns) {
+        if (ok && i < ns && j < np) {
             for (int T = 0; T < n_mbf; ++T) {
                 const double2 x = Xf[j * ldx + i * n_mbf + T];
                 const double2 ww = w[T];
@@ -89,33 +95,36 @@ using namespace harp;
 namespace {
 
 harp_status rhs_launch(const void* d_models, int64_t model_stride, int32_t n_mat, int32_t n_mbf, int32_t n_ant,
-                       void* d_B, int64_t ldb, int64_t stride_b, const harp_system* d_sys, int32_t n_models,
-                       hipStream_t stream) {
-    if (!d_models || !d_B || n_mat <= 0 || n_mat > 65535 || n_mbf <= 0 || n_ant <= 0) return HARP_E_ARG;
+                       int32_t n_cols, void* d_B, int64_t ldb, int64_t stride_b, const harp_system* d_sys,
+                       int32_t n_models, hipStream_t stream) {
+    if (!d_models || !d_B || n_mat <= 0 || n_mat > 65535 || n_mbf <= 0 || n_ant <= 0 || n_cols <= 0)
+        return HARP_E_ARG;
     const int64_t n = int64_t(n_ant) * n_mbf;
-    if (ldb < n || (n_mat > 1 && stride_b < ldb * n_ant)) return HARP_E_ARG;
-    const int64_t total = n * n_ant;
+    if (ldb < n || (n_mat > 1 && stride_b < ldb * n_cols)) return HARP_E_ARG;
+    const int64_t total = n * n_cols;
     const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
     HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
                      hipLaunchKernelGGL(port_rhs_kernel, dim3(blocks, unsigned(n_mat)), dim3(256), 0, stream,
-                                        static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                                        static_cast<const char*>(d_models), model_stride, n_mbf, n_ant, n_cols,
                                         static_cast<double2*>(d_B), ldb, stride_b, d_sys, n_models));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
 
 harp_status admittance_launch(const void* d_models, int64_t model_stride, int32_t n_mat, int32_t n_mbf,
-                              int32_t n_ant, const void* d_X, int64_t ldx, int64_t stride_x, void* d_Y, int64_t ldy,
-                              int64_t stride_y, const harp_system* d_sys, int32_t n_models, hipStream_t stream) {
-    if (!d_models || !d_X || !d_Y || n_mat <= 0 || n_mat > 65535 || n_mbf <= 0 || n_ant <= 0) return HARP_E_ARG;
+                              int32_t n_ant, int32_t n_cols, const void* d_X, int64_t ldx, int64_t stride_x,
+                              void* d_Y, int64_t ldy, int64_t stride_y, const harp_system* d_sys, int32_t n_models,
+                              hipStream_t stream) {
+    if (!d_models || !d_X || !d_Y || n_mat <= 0 || n_mat > 65535 || n_mbf <= 0 || n_ant <= 0 || n_cols <= 0)
+        return HARP_E_ARG;
     const int64_t n = int64_t(n_ant) * n_mbf;
     if (ldx < n || ldy < n_ant) return HARP_E_ARG;
-    if (n_mat > 1 && (stride_x < ldx * n_ant || stride_y < ldy * n_ant)) return HARP_E_ARG;
-    const int64_t total = int64_t(n_ant) * n_ant;
+    if (n_mat > 1 && (stride_x < ldx * n_cols || stride_y < ldy * n_cols)) return HARP_E_ARG;
+    const int64_t total = int64_t(n_ant) * n_cols;
     const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
     HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
                      hipLaunchKernelGGL(port_admittance_kernel, dim3(blocks, unsigned(n_mat)), dim3(256), 0,
-                                        stream, static_cast<const char*>(d_models), model_stride, n_mbf, n_ant,
+                                        stream, static_cast<const char*>(d_models), model_stride, n_mbf, n_ant, n_cols,
                                         static_cast<const double2*>(d_X), ldx, stride_x, static_cast<double2*>(d_Y),
                                         ldy, stride_y, d_sys, n_models));
     HARP_LAUNCH_CHECK();
@@ -127,31 +136,32 @@ harp_status admittance_launch(const void* d_models, int64_t model_stride, int32_
 extern "C" harp_status harp_port_rhs(const void* d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
                                      int32_t n_ant, void* d_B, int64_t ldb, int64_t stride_b,
                                      hipStream_t stream) {
-    return rhs_launch(d_models, model_stride, n_freq, n_mbf, n_ant, d_B, ldb, stride_b, nullptr, 0, stream);
+    return rhs_launch(d_models, model_stride, n_freq, n_mbf, n_ant, n_ant, d_B, ldb, stride_b, nullptr, 0, stream);
 }
 
 extern "C" harp_status harp_port_admittance(const void* d_models, int64_t model_stride, int32_t n_freq,
                                             int32_t n_mbf, int32_t n_ant, const void* d_X, int64_t ldx,
                                             int64_t stride_x, void* d_Y, int64_t ldy, int64_t stride_y,
                                             hipStream_t stream) {
-    return admittance_launch(d_models, model_stride, n_freq, n_mbf, n_ant, d_X, ldx, stride_x, d_Y, ldy, stride_y,
-                             nullptr, 0, stream);
+    return admittance_launch(d_models, model_stride, n_freq, n_mbf, n_ant, n_ant, d_X, ldx, stride_x, d_Y, ldy,
+                             stride_y, nullptr, 0, stream);
 }
 
 extern "C" harp_status harp_port_rhs_systems(const void* d_models, int64_t model_stride, int32_t n_models,
                                              int32_t n_mbf, const harp_system* d_sys, int32_t n_sys,
-                                             int32_t n_ant_pad, void* d_B, int64_t ldb, int64_t stride_b,
-                                             hipStream_t stream) {
+                                             int32_t n_ant_pad, int32_t n_ports_pad, void* d_B, int64_t ldb,
+                                             int64_t stride_b, hipStream_t stream) {
     if (!d_sys || n_models <= 0) return HARP_E_ARG;
-    return rhs_launch(d_models, model_stride, n_sys, n_mbf, n_ant_pad, d_B, ldb, stride_b, d_sys, n_models, stream);
+    return rhs_launch(d_models, model_stride, n_sys, n_mbf, n_ant_pad, n_ports_pad, d_B, ldb, stride_b, d_sys,
+                      n_models, stream);
 }
 
 extern "C" harp_status harp_port_admittance_systems(const void* d_models, int64_t model_stride, int32_t n_models,
                                                     int32_t n_mbf, const harp_system* d_sys, int32_t n_sys,
-                                                    int32_t n_ant_pad, const void* d_X, int64_t ldx,
-                                                    int64_t stride_x, void* d_Y, int64_t ldy, int64_t stride_y,
-                                                    hipStream_t stream) {
+                                                    int32_t n_ant_pad, int32_t n_ports_pad, const void* d_X,
+                                                    int64_t ldx, int64_t stride_x, void* d_Y, int64_t ldy,
+                                                    int64_t stride_y, hipStream_t stream) {
     if (!d_sys || n_models <= 0) return HARP_E_ARG;
-    return admittance_launch(d_models, model_stride, n_sys, n_mbf, n_ant_pad, d_X, ldx, stride_x, d_Y, ldy,
-                             stride_y, d_sys, n_models, stream);
+    return admittance_launch(d_models, model_stride, n_sys, n_mbf, n_ant_pad, n_ports_pad, d_X, ldx, stride_x, d_Y,
+                             ldy, stride_y, d_sys, n_models, stream);
 }

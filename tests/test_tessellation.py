@@ -1,0 +1,131 @@
+"""The overlapping-subarray tessellation (Section II-D): pins of the oracle's
+geometry and solution, and the library's host tessellation (harp_tessellate)
+against the oracle's, list for list (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fill as ofill, patterns as opat, solve as osolve
+from oracle import tessellation as ot
+from workloads import directions, layout_disk, workload
+
+from parity import oracle_models
+
+
+def test_inner_hexagons_tile_the_plane():
+    """The nearest lattice centre's inner hexagon contains the point, and no
+    other centre's inner hexagon does (away from edges): spacing, orientation
+    and circumradius of the lattice agree."""
+    rng = np.random.default_rng(1)
+    r = 2.5
+    px, py = rng.uniform(-20, 20, 4000), rng.uniform(-20, 20, 4000)
+    cen = ot.lattice_centres(px, py, r)
+    C = np.array([[c[2], c[3]] for c in cen])
+    d2 = (px[:, None] - C[None, :, 0]) ** 2 + (py[:, None] - C[None, :, 1]) ** 2
+    own = np.argmin(d2, axis=1)
+    hits = np.zeros(px.size, dtype=int)
+    for k, (cx, cy) in enumerate(C):
+        inside = ot.in_hexagon(px, py, ot.hexagon_vertices(cx, cy, r))
+        assert inside[own == k].all()
+        hits += inside
+    assert (hits == 1).mean() > 0.99 and (hits >= 1).all()
+    # the hexagon's area matches the lattice cell area (sqrt(3) r)^2 sqrt(3)/2
+    v = ot.hexagon_vertices(0.0, 0.0, r)
+    area = 0.5 * abs(np.dot(v[:, 0], np.roll(v[:, 1], -1)) - np.dot(v[:, 1], np.roll(v[:, 0], -1)))
+    assert math.isclose(area, 3.0 * r * r * math.sqrt(3.0) / 2.0, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("r_ext,expect", [(0.99, 1), (1.01, 7)])
+def test_lattice_layout_neighbours(r_ext, expect):
+    """Antennas on the cell centres: the six neighbours sit at hexagonal radius
+    2 R_in, so an outer radius just below / above 2 R_in holds 1 / 7 antennas
+    (except on the rim of the patch)."""
+    r = 3.0
+    pts = [(1.5 * r * i, math.sqrt(3.0) * r * (j + 0.5 * i)) for i in range(-4, 5) for j in range(-4, 5)]
+    x, y = np.array(pts).T
+    cells = ot.tessellate(x, y, r, r_ext * r)
+    assert all(ni == 1 for _, _, ni in cells) and len(cells) == x.size
+    centre = [c for c in cells if abs(c[0][0]) < 1e-9 and abs(c[0][1]) < 1e-9][0]
+    assert centre[1].size == expect
+
+
+def test_every_antenna_in_exactly_one_inner_part():
+    wl = workload("cfg5")
+    for r_ext in (0.0, 6.0):
+        cells = ot.tessellate(wl.x, wl.y, 6.0, r_ext)
+        inner = np.concatenate([m[:ni] for _, m, ni in cells])
+        assert np.array_equal(np.sort(inner), np.arange(wl.n_ant))
+        for (cx, cy), m, ni in cells:
+            assert ot.in_hexagon(wl.x[m], wl.y[m], ot.hexagon_vertices(cx, cy, 6.0 + r_ext)).all()
+            if r_ext == 0.0:
+                assert m.size == ni
+
+
+def test_whole_array_limit_equals_full_solve():
+    """With the outer hexagon covering the whole array every subarray is the
+    array: X, Y and the patterns are those of the full solve."""
+    wl, models = oracle_models("cfg1")
+    m = models[0]
+    th, ph = directions(40, seed=3)
+    res, E = ot.solve_tessellated(m, wl.x, wl.y, 2.0, 100.0, th, ph)
+    Z = ofill.fill(m, wl.x, wl.y)
+    X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
+    Y = osolve.admittance(X, m.w, wl.n_ant)
+    Ef = opat.embedded_patterns(m.freq, m.samples, wl.x, wl.y, X, th, ph)
+    assert len(ot.tessellate(wl.x, wl.y, 2.0, 100.0)) > 1
+    for a, (mem, xa, ya) in enumerate(res):
+        assert np.array_equal(np.sort(mem), np.arange(wl.n_ant))
+        inv = np.argsort(mem)
+        xa_full = xa.reshape(-1, m.n_mbf)[inv].ravel()
+        assert np.linalg.norm(xa_full - X[:, a]) <= 1e-12 * np.linalg.norm(X[:, a])
+        assert np.linalg.norm(ya[inv] - Y[:, a]) <= 1e-12 * np.linalg.norm(Y[:, a])
+    assert np.linalg.norm(E - Ef) <= 1e-12 * np.linalg.norm(Ef)
+
+
+def test_error_falls_as_the_extension_grows():
+    """Section IV-B: the EEP error of the tessellated solution against the full
+    solution decreases as R_ext grows (120 elements, R_in = 3 m)."""
+    from oracle import fit as ofit
+    from workloads import element
+    el = element(4, 32, seed=201)
+    m = ofit.fit(150e6, el.samples, 7, 6, 1.5, wire_radius=el.wire_radius)
+    x, y = layout_disk(120, 13.0, 1.5, seed=77)
+    th, ph = directions(64, seed=5)
+    X = osolve.solve(ofill.fill(m, x, y), osolve.port_rhs(m.w, x.size))
+    Ef = opat.embedded_patterns(m.freq, m.samples, x, y, X, th, ph)
+    errs = []
+    for r_ext in (0.0, 1.5, 3.0, 6.0):
+        _, E = ot.solve_tessellated(m, x, y, 3.0, r_ext, th, ph)
+        errs.append(np.mean(np.linalg.norm((E - Ef).reshape(x.size, -1), axis=1)
+                            / np.linalg.norm(Ef.reshape(x.size, -1), axis=1)))
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1702_03781_amd import api as A
+    return A
+
+
+@pytest.mark.parametrize("r_in,r_ext", [(6.0, 0.0), (6.0, 6.0), (10.0, 5.0), (4.0, 12.0), (3.0, 100.0)])
+def test_library_tessellation_matches_oracle(api, r_in, r_ext):
+    wl = workload("cfg5")
+    a = api.harp_tessellate(wl.x, wl.y, r_in, r_ext, origin=(0.3, -1.1))
+    b = ot.tessellate(wl.x, wl.y, r_in, r_ext, origin=(0.3, -1.1))
+    assert len(a) == len(b)
+    for ca, (cen, mem, ni) in zip(a, b):
+        assert ca.n_inner == ni and np.array_equal(ca.members, mem)
+        assert np.allclose(ca.center, cen, rtol=0, atol=1e-12)
+
+
+def test_library_tessellation_edge_cases(api):
+    from paper_1702_03781_amd._lib import HarpError
+    one = api.harp_tessellate(np.array([1.0]), np.array([2.0]), 5.0, 5.0)
+    assert len(one) == 1 and one[0].n_inner == 1 and list(one[0].members) == [0]
+    x, y = layout_disk(30, 2.0, 0.3, seed=4)
+    allin = api.harp_tessellate(x, y, 50.0, 0.0)
+    assert len(allin) == 1 and allin[0].n_inner == 30
+    for bad in [(0.0, 1.0), (1.0, -1.0), (float("nan"), 1.0)]:
+        with pytest.raises(HarpError):
+            api.harp_tessellate(x, y, *bad)
