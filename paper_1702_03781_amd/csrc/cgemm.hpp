@@ -81,8 +81,8 @@ template <typename T> struct alignas(16) Vec16 {
     typename Mfma<T>::c_t v[16 / sizeof(typename Mfma<T>::c_t)];
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC>
-__global__ void __launch_bounds__(256) cgemm_kernel(GemmArgs<T> g) {
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1>
+__global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     using ct = typename Mfma<T>::c_t;
     using acc_t = typename Mfma<T>::acc_t;
     constexpr int NV = int(16 / sizeof(ct));          // complex per 16-byte access
@@ -273,16 +273,16 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
            ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1>
 inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
     const int cls = sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64;
     if (gemm_vec_ok(g))
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC>), grid,
                              dim3(256), 0, g);
     else
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC>), grid,
                              dim3(256), 0, g);
 }
 

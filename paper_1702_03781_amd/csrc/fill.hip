@@ -16,13 +16,19 @@
 // entry, 8 (complex64) or 16 (complex128) bytes written: the fill is bound by
 // the vector ALU, not by HBM.
 //
-// Mapping: a 256-thread workgroup owns 64 testing antennas (one per lane) x
-// 16 source antennas (4 waves x G = 4 per thread).  All lanes of a wave walk
-// the same (T, S, p, q) sequence, so the coefficient stream is wave-uniform
-// and is read through the scalar cache; per-pair geometry lives in VGPRs and
-// is reused for all N_m^2 entries of the block.  Lanes hold consecutive m, so
-// for each (S, T) a wave writes a 64-row strided column segment; the eight T
-// values of one column complete the 512-byte runs in L2 before eviction.
+// Mapping.  The reduced matrix is column-major with the MBF index fastest
+// (row m N_m + T), so a run of consecutive rows is (antenna, testing MBF)
+// with T fastest.  A lane therefore owns one testing antenna m and one
+// testing MBF T (lane = N_m i + T, i < 64 / N_m, at most 16 antennas), and
+// G = 4 source antennas; the four waves of a 256-thread workgroup take
+// 4 x G = 16 consecutive source antennas.  For each source MBF S a store
+// instruction then writes 64 consecutive rows of one column (1 KB of
+// complex128): every store is a full, contiguous run.  Because the
+// coefficients C^{TS} now differ across the lanes of a wave (by T), the
+// coefficients of the current S for every T are staged in LDS as [p][q][T]
+// (a wave reads N_m consecutive complex values per (p, q): no bank
+// conflicts) and shared by the G source antennas of a lane.  The pair
+// geometry (t, w, phase, block kind) is computed once per pair into LDS.
 #include <math.h>
 
 #include "common.hpp"
@@ -31,9 +37,16 @@
 namespace harp {
 namespace {
 
-constexpr int kTileM = 64;   // testing antennas per workgroup (lanes)
-constexpr int kG = 4;        // source antennas per thread
-constexpr int kTileN = 4 * kG;
+constexpr int kWaves = 4;
+constexpr int kG = 4;                  // source antennas per lane
+constexpr int kTileN = kWaves * kG;    // source antennas per workgroup
+constexpr int kMaxPPW = 16;            // testing antennas per workgroup (cap)
+constexpr int kMaxPairs = kMaxPPW * kTileN;
+constexpr int kMaxMbf = 64;            // one testing antenna needs N_m lanes
+constexpr int kMaxCoefLds = 65536;     // bytes of the staged coefficients of one S
+
+// testing antennas per workgroup: N_m lanes each, at most 64 lanes and kMaxPPW
+__host__ __device__ inline int fill_ppw(int n_mbf) { return 64 / n_mbf < kMaxPPW ? 64 / n_mbf : kMaxPPW; }
 
 struct FillArgs {
     const char* models;
@@ -75,15 +88,24 @@ template <> struct FillTraits<double> {
 // kPad: identity block of a padding antenna (unit diagonal, zeros elsewhere)
 enum PairKind : int { kSkip = 0, kHarp = 1, kSelf = 2, kZero = 3, kPad = 4 };
 
+template <typename R> struct alignas(16) PairGeo {
+    R t[kMaxPairs];
+    R wr[kMaxPairs], wi[kMaxPairs];
+    R pr[kMaxPairs], pi[kMaxPairs];
+    int kind[kMaxPairs];
+};
+
 // The pointers are separate __restrict__ parameters (not struct members) so
-// that the compiler may read the model through the scalar cache.
+// that the compiler may keep the model reads in the scalar cache.
 template <typename R, int Q, bool DUAL>
 __global__ void __launch_bounds__(256)
     fill_kernel(FillArgs a, const char* __restrict__ models, const double* __restrict__ px,
                 const double* __restrict__ py, void* __restrict__ Zout, float* __restrict__ Z32out) {
+    extern __shared__ __attribute__((aligned(16))) char fill_smem[];   // [np][Q+1][N_m] complex R
+    __shared__ PairGeo<R> geo;
     const int f = blockIdx.y;
     // antennas of this system (ns <= a.n_ant; the rest of the order is padding)
-    int mi = f, ns = a.n_ant;
+    int mi_model = f, ns = a.n_ant;
     if (a.sys) {
         const harp_system d = a.sys[f];
         if (d.model < 0 || d.model >= a.n_models || d.n_ant < 1 || d.n_ant > a.n_ant || d.pos < 0 ||
@@ -91,12 +113,12 @@ __global__ void __launch_bounds__(256)
             if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(a.info + f, -2);
             return;
         }
-        mi = d.model;
+        mi_model = d.model;
         ns = d.n_ant;
         px += d.pos;
         py += d.pos;
     }
-    const char* model = models + size_t(mi) * a.model_stride;
+    const char* model = models + size_t(mi_model) * a.model_stride;
     const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
     const int P = h->P;
     if (h->magic != kModelMagic || h->n_mbf != a.n_mbf || h->Q != Q || P > a.p_max || P < 0) {
@@ -106,55 +128,53 @@ __global__ void __launch_bounds__(256)
     const int nm = a.n_mbf;
     const int np = 2 * P + 1;
     const double k = h->k, r_min = h->r_min;
-
-    const int tiles_m = (a.n_ant + kTileM - 1) / kTileM;
+    const int ppw = fill_ppw(nm);
+    const int tiles_m = (a.n_ant + ppw - 1) / ppw;
     const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    const int m = tm * kTileM + lane;
+    const int m0 = tm * ppw, n0 = tn * kTileN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    int kind[kG];
-    R t[kG];
-    cpx<R> w[kG], ph[kG];
+    // 1. geometry of the workgroup's pairs, one thread per pair
     int n_below = 0;
-    const double xm = m < ns ? px[m] : 0.0;
-    const double ym = m < ns ? py[m] : 0.0;
-#pragma unroll
-    for (int g = 0; g < kG; ++g) {
-        const int n = tn * kTileN + wave * kG + g;
-        kind[g] = kSkip;
-        t[g] = R(0);
-        w[g] = cpx<R>{R(1), R(0)};
-        ph[g] = cpx<R>{R(0), R(0)};
-        if (m >= a.n_ant || n >= a.n_ant) continue;
-        if (m >= ns || n >= ns) {
-            kind[g] = m == n ? kPad : kZero;
-            continue;
+    for (int e = tid; e < ppw * kTileN; e += 256) {
+        const int ii = e % ppw, jj = e / ppw;
+        const int m = m0 + ii, n = n0 + jj;
+        int kind = kSkip;
+        R t = R(0), wr = R(1), wi = R(0), pr = R(0), pim = R(0);
+        if (m < a.n_ant && n < a.n_ant) {
+            if (m >= ns || n >= ns) {
+                kind = m == n ? kPad : kZero;
+            } else if (m == n) {
+                kind = kSelf;
+            } else {
+                const double dx = px[m] - px[n], dy = py[m] - py[n];
+                const double r = sqrt(dx * dx + dy * dy);
+                if (a.ri > 0.0 && r > a.ri) {
+                    kind = kZero;
+                } else {
+                    kind = kHarp;
+                    if (r < r_min * (1.0 - 1e-12)) ++n_below;
+                    const double ir = 1.0 / r;
+                    t = R(r_min * ir);
+                    wr = R(dx * ir);
+                    wi = R(dy * ir);
+                    // phase angle -k r - P alpha, reduced to [-pi, pi] in FP64
+                    double th = -k * r - double(P) * atan2(dy, dx);
+                    th -= kTwoPi * rint(th * (1.0 / kTwoPi));
+                    if constexpr (sizeof(R) == 4) {
+                        sincosf(float(th), &pim, &pr);
+                    } else {
+                        sincos(th, &pim, &pr);
+                    }
+                }
+            }
         }
-        if (m == n) {
-            kind[g] = kSelf;
-            continue;
-        }
-        const double dx = xm - px[n], dy = ym - py[n];
-        const double r = sqrt(dx * dx + dy * dy);
-        if (a.ri > 0.0 && r > a.ri) {
-            kind[g] = kZero;
-            continue;
-        }
-        kind[g] = kHarp;
-        if (r < r_min * (1.0 - 1e-12)) ++n_below;
-        const double ir = 1.0 / r;
-        t[g] = R(r_min * ir);
-        w[g] = cpx<R>{R(dx * ir), R(dy * ir)};
-        // phase angle -k r - P alpha, reduced to [-pi, pi] in FP64
-        double th = -k * r - double(P) * atan2(dy, dx);
-        th -= kTwoPi * rint(th * (1.0 / kTwoPi));
-        R s, c;
-        if constexpr (sizeof(R) == 4) {
-            sincosf(float(th), &s, &c);
-        } else {
-            sincos(th, &s, &c);
-        }
-        ph[g] = cpx<R>{c, s};
+        geo.t[e] = t;
+        geo.wr[e] = wr;
+        geo.wi[e] = wi;
+        geo.pr[e] = pr;
+        geo.pi[e] = pim;
+        geo.kind[e] = kind;
     }
     // domain count: one atomic per wave
     {
@@ -162,90 +182,121 @@ __global__ void __launch_bounds__(256)
         for (int off = 32; off > 0; off >>= 1) cnt += __shfl_down(cnt, off, 64);
         if (lane == 0 && cnt) atomicAdd(a.info + f, cnt);
     }
-    bool any_harp_lane = false;
-#pragma unroll
-    for (int g = 0; g < kG; ++g) any_harp_lane |= (kind[g] == kHarp);
-    const bool wave_harp = __ballot(any_harp_lane) != 0;
+    __syncthreads();
 
-    const R* coef = FillTraits<R>::coef(model, h);
+    // 2. this lane: testing antenna m = m0 + mi, testing MBF T, G source antennas
+    const int mi = lane / nm, T = lane % nm;
+    const bool lane_on = mi < ppw;
+    const int m = m0 + mi;
+    int kind[kG];
+    R t[kG];
+    cpx<R> w[kG], ph[kG];
+    bool any_harp = false;
+#pragma unroll
+    for (int g = 0; g < kG; ++g) {
+        const int e = (wave * kG + g) * ppw + (lane_on ? mi : 0);
+        kind[g] = lane_on ? geo.kind[e] : int(kSkip);
+        t[g] = geo.t[e];
+        w[g] = cpx<R>{geo.wr[e], geo.wi[e]};
+        ph[g] = cpx<R>{geo.pr[e], geo.pi[e]};
+        any_harp |= (kind[g] == kHarp);
+    }
+    const bool wave_harp = __ballot(any_harp) != 0;
+
+    const R* coef = FillTraits<R>::coef(model, h);         // [T][S][p][q] complex
     const double* zself = reinterpret_cast<const double*>(model + h->off_self);
+    R* cf = reinterpret_cast<R*>(fill_smem);                // [p][q][T] complex
+    const int npq = np * (Q + 1);
     using store_t = typename FillTraits<R>::store_t;
     store_t* Zf = reinterpret_cast<store_t*>(Zout) + size_t(f) * a.stride_z;
     float2* Z32f = DUAL ? reinterpret_cast<float2*>(Z32out) + size_t(f) * a.stride32 : nullptr;
 
     for (int S = 0; S < nm; ++S) {
-        for (int T = 0; T < nm; ++T) {
-            const int ts = T * nm + S;
-            cpx<R> acc[kG];
+        // 3. stage C^{TS}_{pq} of every T for this S
+        __syncthreads();
+        for (int e = tid; e < nm * npq; e += 256) {
+            const int Tc = e / npq, pq = e % npq;
+            const R* src = coef + 2 * (size_t(Tc * nm + S) * npq + pq);
+            cf[2 * (pq * nm + Tc)] = src[0];
+            cf[2 * (pq * nm + Tc) + 1] = src[1];
+        }
+        __syncthreads();
+        // 4. two-level Horner for the lane's G source antennas
+        cpx<R> acc[kG];
 #pragma unroll
-            for (int g = 0; g < kG; ++g) acc[g] = cpx<R>{R(0), R(0)};
-            if (wave_harp) {
-                const R* cts = coef + size_t(ts) * np * (Q + 1) * 2;
-                for (int pp = np - 1; pp >= 0; --pp) {
-                    const R* cq = cts + pp * (Q + 1) * 2;
-                    R cr[Q + 1], ci[Q + 1];
+        for (int g = 0; g < kG; ++g) acc[g] = cpx<R>{R(0), R(0)};
+        if (wave_harp) {
+            for (int pp = np - 1; pp >= 0; --pp) {
+                R cr[Q + 1], ci[Q + 1];
 #pragma unroll
-                    for (int q = 0; q <= Q; ++q) {
-                        cr[q] = cq[2 * q];
-                        ci[q] = cq[2 * q + 1];
+                for (int q = 0; q <= Q; ++q) {
+                    const R* c = cf + 2 * ((pp * (Q + 1) + q) * nm + T);
+                    cr[q] = c[0];
+                    ci[q] = c[1];
+                }
+#pragma unroll
+                for (int g = 0; g < kG; ++g) {
+                    R hr = cr[Q], hi = ci[Q];
+#pragma unroll
+                    for (int q = Q - 1; q >= 0; --q) {
+                        hr = fma(hr, t[g], cr[q]);
+                        hi = fma(hi, t[g], ci[q]);
                     }
-#pragma unroll
-                    for (int g = 0; g < kG; ++g) {
-                        R hr = cr[Q], hi = ci[Q];
-#pragma unroll
-                        for (int q = Q - 1; q >= 0; --q) {
-                            hr = fma(hr, t[g], cr[q]);
-                            hi = fma(hi, t[g], ci[q]);
-                        }
-                        // acc = acc * w + h
-                        const R nr = fma(acc[g].re, w[g].re, fma(-acc[g].im, w[g].im, hr));
-                        const R ni = fma(acc[g].re, w[g].im, fma(acc[g].im, w[g].re, hi));
-                        acc[g].re = nr;
-                        acc[g].im = ni;
-                    }
+                    // acc = acc * w + h
+                    const R nr = fma(acc[g].re, w[g].re, fma(-acc[g].im, w[g].im, hr));
+                    const R ni = fma(acc[g].re, w[g].im, fma(acc[g].im, w[g].re, hi));
+                    acc[g].re = nr;
+                    acc[g].im = ni;
                 }
             }
-            const double sr = zself[2 * ts], si = zself[2 * ts + 1];
+        }
+        // 5. entries (m, T; n, S): consecutive lanes write consecutive rows
+        const double sr = zself[2 * (T * nm + S)], si = zself[2 * (T * nm + S) + 1];
+        const size_t row = size_t(m) * nm + T;
 #pragma unroll
-            for (int g = 0; g < kG; ++g) {
-                if (kind[g] == kSkip) continue;
-                const int n = tn * kTileN + wave * kG + g;
-                cpx<R> z;
-                if (kind[g] == kHarp) {
-                    z = cmul(acc[g], ph[g]);
-                } else if (kind[g] == kSelf) {
-                    z = cpx<R>{R(sr), R(si)};
-                } else if (kind[g] == kPad) {
-                    z = cpx<R>{R(T == S ? 1 : 0), R(0)};
-                } else {
-                    z = cpx<R>{R(0), R(0)};
-                }
-                const size_t row = size_t(m) * nm + T;
-                const size_t col = size_t(n) * nm + S;
-                store_t v;
-                v.x = z.re;
-                v.y = z.im;
-                Zf[col * a.ldz + row] = v;
-                if constexpr (DUAL) {
-                    float2 v32;
-                    v32.x = float(z.re);
-                    v32.y = float(z.im);
-                    Z32f[col * a.ld32 + row] = v32;
-                }
+        for (int g = 0; g < kG; ++g) {
+            if (kind[g] == kSkip) continue;
+            const int n = n0 + wave * kG + g;
+            cpx<R> z;
+            if (kind[g] == kHarp) {
+                z = cmul(acc[g], ph[g]);
+            } else if (kind[g] == kSelf) {
+                z = cpx<R>{R(sr), R(si)};
+            } else if (kind[g] == kPad) {
+                z = cpx<R>{R(T == S ? 1 : 0), R(0)};
+            } else {
+                z = cpx<R>{R(0), R(0)};
+            }
+            const size_t col = size_t(n) * nm + S;
+            store_t v;
+            v.x = z.re;
+            v.y = z.im;
+            Zf[col * a.ldz + row] = v;
+            if constexpr (DUAL) {
+                float2 v32;
+                v32.x = float(z.re);
+                v32.y = float(z.im);
+                Z32f[col * a.ld32 + row] = v32;
             }
         }
     }
 }
 
+// bytes of the staged coefficients of one source MBF
+inline size_t fill_lds_bytes(const FillArgs& a, size_t real_bytes) {
+    return size_t(2 * a.p_max + 1) * (a.Q + 1) * a.n_mbf * 2 * real_bytes;
+}
+
 template <typename R, bool DUAL>
 harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
+    const size_t lds = fill_lds_bytes(a, sizeof(R));
     switch (a.Q) {
 #define HARP_FILL_CASE(QQ)                                                                 \
     case QQ:                                                                               \
         HARP_PROF_EXT_LAUNCH(HARP_K_FILL, stream, 0.0,                                     \
                              double(a.n_freq) * double(a.n_ant) * a.n_mbf * double(a.n_ant) * \
                                  a.n_mbf * (DUAL ? 24.0 : double(2 * sizeof(R))),          \
-                             (fill_kernel<R, QQ, DUAL>), grid, dim3(256), 0, a, a.models,  \
+                             (fill_kernel<R, QQ, DUAL>), grid, dim3(256), lds, a, a.models, \
                              a.x, a.y, a.Z, a.Z32);                                        \
         break;
         HARP_FILL_CASE(2)
@@ -265,7 +316,8 @@ harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
 
 harp_status fill_launch(FillArgs& a, harp_dtype dtype, hipStream_t stream) {
     if (!a.models || !a.x || !a.y || !a.Z || !a.info) return HARP_E_ARG;
-    if (a.n_freq <= 0 || a.n_mbf <= 0 || a.n_ant <= 0 || a.Q < 2 || a.Q > 8 || a.p_max < 0) return HARP_E_ARG;
+    if (a.n_freq <= 0 || a.n_mbf <= 0 || a.n_mbf > kMaxMbf || a.n_ant <= 0 || a.Q < 2 || a.Q > 8 || a.p_max < 0)
+        return HARP_E_ARG;
     if (a.n_freq > 65535) return HARP_E_ARG;
     if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
     if (!isfinite(a.ri)) return HARP_E_ARG;
@@ -276,11 +328,13 @@ harp_status fill_launch(FillArgs& a, harp_dtype dtype, hipStream_t stream) {
         if (dtype != HARP_C128) return HARP_E_ARG;
         if (a.ld32 < n || (a.n_freq > 1 && a.stride32 < a.ld32 * n)) return HARP_E_ARG;
     }
+    if (fill_lds_bytes(a, dtype == HARP_C64 ? 4 : 8) > size_t(kMaxCoefLds)) return HARP_E_ARG;
     HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
                      hipLaunchKernelGGL(fill_info_init, dim3((a.n_freq + 255) / 256), dim3(256), 0, stream, a.info,
                                         a.n_freq));
     HARP_LAUNCH_CHECK();
-    const int tiles = ((a.n_ant + kTileM - 1) / kTileM) * ((a.n_ant + kTileN - 1) / kTileN);
+    const int ppw = fill_ppw(a.n_mbf);
+    const int tiles = ((a.n_ant + ppw - 1) / ppw) * ((a.n_ant + kTileN - 1) / kTileN);
     const dim3 grid{unsigned(tiles), unsigned(a.n_freq), 1u};
     if (dtype == HARP_C64) return launch_fill_q<float, false>(a, grid, stream);
     if (a.Z32) return launch_fill_q<double, true>(a, grid, stream);

@@ -840,7 +840,8 @@ __global__ void sumsq_final_kernel(const double* __restrict__ part, double* __re
 // ---------------------------------------------------------------------------
 
 template <typename T> struct LuCfg {
-    static constexpr int NB = 64;   // outer block (row/column block of the trailing update)
+    static constexpr int NB = 64;   // outer block: panels, row exchanges and block-row solve
+    static constexpr int NS = 4;    // outer blocks per trailing update (its contraction is NS * NB)
 };
 
 // Panel width: the register-resident panel holds RPT x W complex values per
@@ -922,67 +923,93 @@ GemmArgs<T> sub_gemm(T* base, int64_t ld, int64_t s, int M, int N, int K, int ar
 template <typename T>
 harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t* ipiv, int32_t* info, void* blk,
                         hipStream_t st) {
-    constexpr int NB = LuCfg<T>::NB;
+    // Right-looking blocked LU whose trailing update is deferred over NS outer
+    // blocks (a super-block of NS * NB columns): within a super-block, an
+    // outer block first receives the updates of the earlier outer blocks of
+    // the super-block on its own columns (catch-up), is factored, and its row
+    // block receives the same updates on the columns to its right (deferred
+    // rows) before its block-row solve; the rest of the trailing matrix is
+    // updated once per super-block with a contraction of NS * NB.
+    constexpr int NB = LuCfg<T>::NB, NS = LuCfg<T>::NS;
     static_assert(NB <= NBMAX, "outer block");
     const int W = panel_width<T>(n);
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch));
     HARP_LAUNCH_CHECK();
     harp_status s;
-    for (int k0 = 0; k0 < n; k0 += NB) {
-        const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
-        // row exchanges reach the block row to the right (then the unit-lower
-        // solve and the trailing update) and the earlier columns of the same
-        // solve group (so each group's multipliers share one row order)
-        const int lbeg = (k0 / kSB) * kSB;
-        const bool block_row = kend < n || lbeg < k0;
-        for (int j0 = k0; j0 < kend; j0 += W) {
-            const int w = std::min(W, kend - j0);
-            const bool last = j0 + w == kend;
-            PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info, (last && block_row) ? blk : nullptr};
-            if ((s = launch_getf2<T>(pa, W, batch, st)) != HARP_OK) return s;
-            if (j0 + w < kend) {
-                GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - j0 - w, kend - j0 - w, w, j0 + w, j0, j0, j0 + w,
-                                            j0 + w, j0 + w, T(-1), T(1), nullptr);
+    for (int K0 = 0; K0 < n; K0 += NS * NB) {
+        const int Kend = std::min(n, K0 + NS * NB);
+        for (int k0 = K0; k0 < Kend; k0 += NB) {
+            const int nbo = std::min(NB, n - k0), kend = k0 + nbo;
+            // catch-up: A[k0:n, k0:kend] -= L[k0:n, K0:k0] U[K0:k0, k0:kend]
+            if (k0 > K0) {
+                GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - k0, nbo, k0 - K0, k0, K0, K0, k0, k0, k0, T(-1), T(1),
+                                            nullptr);
+                if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+            }
+            // row exchanges reach the block row to the right (then the
+            // unit-lower solve and the trailing update) and the earlier
+            // columns of the same solve group (so each group's multipliers
+            // share one row order)
+            const int lbeg = (k0 / kSB) * kSB;
+            const bool block_row = kend < n || lbeg < k0;
+            for (int j0 = k0; j0 < kend; j0 += W) {
+                const int w = std::min(W, kend - j0);
+                const bool last = j0 + w == kend;
+                PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info, (last && block_row) ? blk : nullptr};
+                if ((s = launch_getf2<T>(pa, W, batch, st)) != HARP_OK) return s;
+                if (j0 + w < kend) {
+                    GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - j0 - w, kend - j0 - w, w, j0 + w, j0, j0, j0 + w,
+                                                j0 + w, j0 + w, T(-1), T(1), nullptr);
+                    if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+                }
+            }
+            if (block_row) {
+                LaswpArgs la{blk, nbo, A, lda, sA, kend, n, lbeg, k0};
+                constexpr int CB = LaswpCols<T>::CB;
+                const int tiles = (n - kend + CB - 1) / CB + (k0 - lbeg + CB - 1) / CB;
+                HARP_PROF_EXT_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0, (laswp_kernel<T>), dim3(tiles, batch), dim3(256),
+                                     0, la);
+                HARP_LAUNCH_CHECK();
+            }
+            if (kend < n) {
+                // deferred rows: A[k0:kend, kend:n] -= L[k0:kend, K0:k0] U[K0:k0, kend:n]
+                if (k0 > K0) {
+                    GemmArgs<T> g = sub_gemm<T>(A, lda, sA, nbo, n - kend, k0 - K0, k0, K0, K0, kend, k0, kend,
+                                                T(-1), T(1), nullptr);
+                    if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+                }
+                // block row U12 = L11^-1 (exchanged rows), in place: one row
+                // tile, so every workgroup reads its whole column block before
+                // writing it
+                GemmArgs<T> g{};
+                g.M = nbo;
+                g.N = n - kend;
+                g.K = nbo;
+                g.A = static_cast<const T*>(blk);
+                g.lda = NBMAX;
+                g.sA = BlkScratch<T>::stride / int64_t(2 * sizeof(T));
+                g.B = A + 2 * (size_t(kend) * lda + k0);
+                g.ldb = lda;
+                g.sB = sA;
+                g.C = nullptr;
+                g.ldc = lda;
+                g.sC = sA;
+                g.D = const_cast<T*>(g.B);
+                g.ldd = lda;
+                g.sD = sA;
+                g.alpha = T(1);
+                g.beta = T(0);
+                g.active = nullptr;
+                static_assert(NBMAX <= 64, "the in-place product needs a single row tile");
                 if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
             }
         }
-        if (block_row) {
-            LaswpArgs la{blk, nbo, A, lda, sA, kend, n, lbeg, k0};
-            constexpr int CB = LaswpCols<T>::CB;
-            const int tiles = (n - kend + CB - 1) / CB + (k0 - lbeg + CB - 1) / CB;
-            HARP_PROF_EXT_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0, (laswp_kernel<T>), dim3(tiles, batch), dim3(256), 0,
-                                 la);
-            HARP_LAUNCH_CHECK();
-        }
-        if (kend < n) {
-            // block row U12 = L11^-1 (exchanged rows), in place: one row tile,
-            // so every workgroup reads its whole column block before writing it
-            GemmArgs<T> g{};
-            g.M = nbo;
-            g.N = n - kend;
-            g.K = nbo;
-            g.A = static_cast<const T*>(blk);
-            g.lda = NBMAX;
-            g.sA = BlkScratch<T>::stride / int64_t(2 * sizeof(T));
-            g.B = A + 2 * (size_t(kend) * lda + k0);
-            g.ldb = lda;
-            g.sB = sA;
-            g.C = nullptr;
-            g.ldc = lda;
-            g.sC = sA;
-            g.D = const_cast<T*>(g.B);
-            g.ldd = lda;
-            g.sD = sA;
-            g.alpha = T(1);
-            g.beta = T(0);
-            g.active = nullptr;
-            static_assert(NBMAX <= 64, "the in-place product needs a single row tile");
-            if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
-        }
-        if (kend < n) {
-            GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - kend, n - kend, nbo, kend, k0, k0, kend, kend, kend, T(-1),
-                                        T(1), nullptr);
+        // trailing update of the super-block:
+        // A[Kend:n, Kend:n] -= L[Kend:n, K0:Kend] U[K0:Kend, Kend:n]
+        if (Kend < n) {
+            GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - Kend, n - Kend, Kend - K0, Kend, K0, K0, Kend, Kend, Kend,
+                                        T(-1), T(1), nullptr);
             if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
         }
     }
