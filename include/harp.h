@@ -128,7 +128,10 @@ harp_status harp_fit(const harp_element *elem, double freq_hz, int32_t P, int32_
  * d_info[f] (int32, device) receives the number of ordered pairs with
  * r < r_min (outside the model; their blocks hold the polynomial continued
  * beyond t = 1), or -1 if model f does not match n_mbf / Q / p_max.
- * Positions d_x, d_y: float64 [n_ant], metres. Asynchronous. */
+ * Positions d_x, d_y: float64 [n_ant], metres.  Limits: n_mbf <= 64, Q in
+ * [2, 8], and the coefficients of one source MBF must fit 64 KB:
+ * n_mbf (2 p_max + 1)(Q + 1) x 16 bytes (complex128) or x 8 (complex64)
+ * <= 65536; HARP_E_ARG otherwise.  Asynchronous. */
 harp_status harp_fill(const void *d_models, int64_t model_stride, int32_t n_freq, int32_t n_mbf,
                       int32_t Q, int32_t p_max, const double *d_x, const double *d_y,
                       int32_t n_ant, double ri, harp_dtype dtype, void *d_Z, int64_t ldz,

@@ -98,6 +98,41 @@ def test_fill_ragged_and_radius_of_influence(api):
             assert info[0] == 0
 
 
+@pytest.mark.parametrize("n_mbf,n_ant", [(20, 23), (1, 40), (64, 5)])
+def test_fill_lane_layouts(api, n_mbf, n_ant):
+    """Element sizes that change the fill's lane layout: 20 MBFs (3 testing
+    antennas per workgroup, 60 of 64 lanes), 1 MBF (16 antennas, 16 lanes),
+    64 MBFs (one antenna per wave); ragged antenna counts, with and without a
+    radius of influence, both precisions."""
+    el = element(n_mbf, 6, seed=300 + n_mbf)
+    x, y = layout_disk(n_ant, 1.2 * np.sqrt(n_ant) + 1.5, 1.2, seed=301 + n_mbf)
+    P, Q = (2, 2) if n_mbf == 64 else (4, 3)
+    mo = ofit.fit(120e6, el.samples, P, Q, 1.2, wire_radius=el.wire_radius)
+    for ri in (0.0, 4.0):
+        Zo = ofill.fill(mo, x, y, ri=ri)
+        for dtype in ("c128", "c64"):
+            Zg, _, info = _gpu_fill(api, [mo], x, y, dtype, ri=ri)
+            eps, zero_ok, _ = block_eps(Zg[0], Zo, n_mbf)
+            assert eps <= FILL_TOL[dtype], (dtype, ri, eps)
+            assert zero_ok and info[0] == 0
+
+
+def test_fill_rejects_oversized_coefficient_slab(api):
+    """The coefficients of one source MBF (all testing MBFs, all p, q) must fit
+    the 64 KB staging area: a synthetic blob of 64 MBFs with P = 8, Q = 6
+    (64 x 17 x 7 complex128 = 122 KB) is refused before anything is enqueued."""
+    nm, P, Q = 64, 8, 6
+    C = np.zeros((nm, nm, 2 * P + 1, Q + 1), dtype=np.complex128)
+    model = api.pack_model(C, np.eye(nm, dtype=np.complex128), np.ones(nm, dtype=np.complex128),
+                           np.zeros((nm, 1, 8)), 1e8, 2.0, 1.0, 1.5, 0.02)
+    mb = api.stack_models([model])
+    xt = torch.zeros(2, dtype=torch.float64, device="cuda")
+    xt[1] = 3.0
+    from paper_1702_03781_amd._lib import HarpError
+    with pytest.raises(HarpError):
+        api.harp_fill(mb, xt, torch.zeros_like(xt), dtype="c128")
+
+
 def test_fill_counts_pairs_below_rmin(api):
     wl, models = oracle_models("cfg1")
     x = wl.x.copy()
