@@ -647,12 +647,14 @@ template <typename T>
 __global__ void __launch_bounds__(256) extract_diag_kernel(const T* __restrict__ LUr, int64_t lda, int64_t sA,
                                                            int n, int G, T* __restrict__ aux) {
     using V = typename C2<T>::t;
-    const int g = blockIdx.x, b = blockIdx.y;
+    // blockIdx.x = group * kXCols + column chunk: kSB / kXCols columns each
+    constexpr int kXCols = 16;
+    const int g = blockIdx.x / kXCols, j0 = (blockIdx.x % kXCols) * (kSB / kXCols), b = blockIdx.y;
     const V* LU = reinterpret_cast<const V*>(LUr) + size_t(b) * sA;
     V* rec = reinterpret_cast<V*>(aux) + (size_t(b) * G + g) * kRec;
     V* Lb = rec;
     V* Ub = rec + int64_t(kSB) * kSB;
-    for (int e = threadIdx.x; e < kSB * kSB; e += 256) {
+    for (int e = j0 * kSB + threadIdx.x; e < (j0 + kSB / kXCols) * kSB; e += 256) {
         const int i = e % kSB, j = e / kSB;
         const int gi = g * kSB + i, gj = g * kSB + j;
         const bool in = gi < n && gj < n;
@@ -1039,8 +1041,8 @@ harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, 
                                         aux_perm(aux, n, batch)));
     HARP_LAUNCH_CHECK();
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                     hipLaunchKernelGGL((extract_diag_kernel<T>), dim3(G, batch), dim3(256), 0, st, LU, lda, sA, n,
-                                        G, aux));
+                     hipLaunchKernelGGL((extract_diag_kernel<T>), dim3(G * 16, batch), dim3(256), 0, st, LU, lda, sA,
+                                        n, G, aux));
     HARP_LAUNCH_CHECK();
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL((tri_inv16_kernel<T>), dim3(G * batch * (kSB / kInv0), 1, 2), dim3(64), 0,

@@ -57,7 +57,10 @@ __global__ void __launch_bounds__(256)
 }
 
 // Y (complex128, n_ant x n_cols per matrix): Y_ij = sum_T w_T X[i N_m + T, j]
-// for antennas i < ns and ports j < np, zero elsewhere; one thread per entry.
+// for antennas i < ns and ports j < np, zero elsewhere.  A wave reads 64
+// consecutive rows of one column of X (N_m lanes per antenna, 64 / N_m
+// antennas), forms w_T x in each lane and sums the N_m lanes of an antenna
+// through LDS: contiguous loads instead of one 16-byte piece per antenna row.
 __global__ void __launch_bounds__(256)
     port_admittance_kernel(const char* __restrict__ models, int64_t model_stride, int n_mbf, int n_ant, int n_cols,
                            const double2* __restrict__ X, int64_t ldx, int64_t stride_x, double2* __restrict__ Y,
@@ -68,22 +71,37 @@ __global__ void __launch_bounds__(256)
     const char* model = models + size_t(ok ? mi : 0) * model_stride;
     const ModelHeader* h = reinterpret_cast<const ModelHeader*>(model);
     const double2* w = reinterpret_cast<const double2*>(model + h->off_port);
-    const int64_t total = int64_t(n_ant) * n_cols;
     const double2* Xf = X + size_t(f) * stride_x;
     double2* Yf = Y + size_t(f) * stride_y;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-         e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t j = e / n_ant, i = e % n_ant;
-        double re = 0.0, im = 0.0;
-        if (ok && i < ns && j < np) {
-            for (int T = 0; T < n_mbf; ++T) {
-                const double2 x = Xf[j * ldx + i * n_mbf + T];
-                const double2 ww = w[T];
-                re += ww.x * x.x - ww.y * x.y;
-                im += ww.x * x.y + ww.y * x.x;
-            }
+    __shared__ double2 part[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = 64 / n_mbf;                     // antennas per wave segment
+    const int ai = lane / n_mbf, T = lane % n_mbf;
+    const int64_t segs = (int64_t(n_ant) + per - 1) / per;
+    const int64_t total = segs * n_cols;            // (segment, column) units, one per wave
+    const double2 wt = w[T < n_mbf ? T : 0];
+    for (int64_t u0 = int64_t(blockIdx.x) * 4; u0 < total; u0 += int64_t(gridDim.x) * 4) {
+        const int64_t u = u0 + wave;
+        const bool unit = u < total;
+        const int64_t j = unit ? u / segs : 0;
+        const int64_t i = unit ? (u % segs) * per + ai : 0;
+        double2 v = {0.0, 0.0};
+        if (unit && ok && ai < per && i < ns && j < np) {
+            const double2 x = Xf[j * ldx + i * n_mbf + T];
+            v.x = wt.x * x.x - wt.y * x.y;
+            v.y = wt.x * x.y + wt.y * x.x;
         }
-        Yf[j * ldy + i] = double2{re, im};
+        part[wave][lane] = v;
+        __syncthreads();
+        if (unit && T == 0 && ai < per && i < n_ant) {
+            double re = 0.0, im = 0.0;
+            for (int t = 0; t < n_mbf; ++t) {
+                re += part[wave][lane + t].x;
+                im += part[wave][lane + t].y;
+            }
+            Yf[j * ldy + i] = double2{re, im};
+        }
+        __syncthreads();
     }
 }
 
@@ -120,8 +138,10 @@ harp_status admittance_launch(const void* d_models, int64_t model_stride, int32_
     const int64_t n = int64_t(n_ant) * n_mbf;
     if (ldx < n || ldy < n_ant) return HARP_E_ARG;
     if (n_mat > 1 && (stride_x < ldx * n_cols || stride_y < ldy * n_cols)) return HARP_E_ARG;
-    const int64_t total = int64_t(n_ant) * n_cols;
-    const unsigned blocks = unsigned(std::min<int64_t>((total + 255) / 256, 4096));
+    if (n_mbf > 64) return HARP_E_ARG;
+    const int per = 64 / n_mbf;
+    const int64_t units = ((int64_t(n_ant) + per - 1) / per) * n_cols;
+    const unsigned blocks = unsigned(std::min<int64_t>((units + 3) / 4, 4096));
     HARP_PROF_LAUNCH(HARP_K_AUX, stream, 0.0, 0.0,
                      hipLaunchKernelGGL(port_admittance_kernel, dim3(blocks, unsigned(n_mat)), dim3(256), 0,
                                         stream, static_cast<const char*>(d_models), model_stride, n_mbf, n_ant, n_cols,
