@@ -79,6 +79,28 @@ def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
+    # the same work for one frequency on one thread
+    one_thread = None
+    try:
+        from threadpoolctl import threadpool_limits
+        m = models[0]
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            Z = ofill.fill(m, wl.x, wl.y)
+            X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
+            osolve.admittance(X, m.w, wl.n_ant)
+            one_thread = wl.n_ant / (time.perf_counter() - t1)
+    except Exception:  # pragma: no cover
+        one_thread = None
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
     return {
         "value": passes * len(freq_idx) * wl.n_ant / dt,
         "unit": "port solves/s",
@@ -89,6 +111,8 @@ def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
                    f"oracle Eq. 4 fill + LAPACK zgesv with {wl.n_ant} RHS + admittances, "
                    f"{dt:.1f} s wall"),
         "seconds": dt,
+        "one_thread_port_solves_per_s": one_thread,
+        "host": {"cpu_model": cpu_model, "nproc": os.cpu_count()},
     }
 
 
@@ -391,16 +415,33 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
-    # timed region (refined path), uninstrumented
+    # timed region (refined path), uninstrumented; an event after every step
+    # (recorded on the stream, no synchronisation) gives per-step durations
     for _ in range(args.warmup):
         ref.step()
     torch.cuda.synchronize()
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    step_ev[0].record()
+    for i in range(args.steps):
         ref.step()
+        step_ev[i + 1].record()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    per_step = sorted(step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps))
     iters = [r["iters"] for r in ref.reports]
+
+    # phases (fill + excitation, factorisation, solve + refinement, admittances)
+    # from events at the phase boundaries of a few more steps
+    phase_names = ["fill_and_excitation", "factor", "solve_and_refine", "admittance"]
+    phase_ms = dict.fromkeys(phase_names, 0.0)
+    n_phase = max(1, min(5, args.steps))
+    for _ in range(n_phase):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ref.step(events=ev)
+        torch.cuda.synchronize()
+        for i, k in enumerate(phase_names):
+            phase_ms[k] += ev[i].elapsed_time(ev[i + 1]) / n_phase
 
     # the same steps again with the library's kernel-class HIP-event timers
     # (each launch bracketed on its own stream) for the per-kernel roofline
@@ -434,7 +475,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": per_step[len(per_step) // 2],
+        "ms_per_step_min": per_step[0],
         "ms_per_step_with_kernel_timers": ms_instr,
+        "phase_ms_per_step": {k: round(v, 4) for k, v in phase_ms.items()},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -555,11 +555,17 @@ class StationSolver:
         self.ws_bytes = ws_b.value
         self.reports = None
 
-    def step(self):
+    def step(self, events=None):
+        """One pass of the hot path.  events: optional five torch.cuda.Event
+        recorded on the stream at the phase boundaries (start, after fill and
+        excitation, after the factorisation, after the solve and refinement,
+        after the admittances)."""
         L = lib()
         mb, n, na, nf = self.models, self.n, self.n_ant, self.models.n_freq
         st = _stream(mb.data.device)
         refined = self.mode == "refined"
+        mark = (lambda i: events[i].record()) if events is not None else (lambda i: None)
+        mark(0)
         pz, ldz, sz = _cm(self.Z64, "Z64")
         p32, ld32, s32 = _cm(self.Z32, "Z32") if refined else (0, 0, 0)
         check(L.harp_fill(_ptr(mb.data), mb.stride, nf, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
@@ -568,10 +574,12 @@ class StationSolver:
         pb, ldb, sb = _cm(self.B, "B")
         check(L.harp_port_rhs(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, pb, ldb, sb, st),
               "harp_port_rhs")
+        mark(1)
         pf, ldf, sf = (p32, ld32, s32) if refined else (pz, ldz, sz)
         dt = C64 if refined else C128
         check(L.reduced_factor(n, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.finfo),
                                _ptr(self.aux), self.aux_bytes, st), "reduced_factor")
+        mark(2)
         px, ldx, sx = _cm(self.X, "X")
         ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter)) if refined else None
         rep = (HarpRefineReport * nf)() if refined else None
@@ -579,9 +587,11 @@ class StationSolver:
                               self.aux_bytes, pb, ldb, sb, px, ldx,
                               sx, ctypes.byref(ref) if ref is not None else None, rep,
                               _ptr(self.ws), self.ws_bytes, st), "reduced_solve")
+        mark(3)
         py, ldy, sy = _cm(self.Y, "Y")
         check(L.harp_port_admittance(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, px, ldx, sx, py,
                                      ldy, sy, st), "harp_port_admittance")
+        mark(4)
         if rep is not None:
             self.reports = [{"iters": r.iters, "converged": bool(r.converged),
                              "resid_rel": r.resid_rel} for r in rep]
