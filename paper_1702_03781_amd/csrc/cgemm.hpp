@@ -289,8 +289,13 @@ inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, do
 // Enqueue D = beta C + alpha A B for `batch` (x g.inner) matrices.  M, N, K
 // may be zero.  eff_batch (< 0: batch) is the number of outer matrices not
 // skipped by g.active, used only for the work accounting of the profiler.
-// Narrow products (N <= 32: the LU's in-block updates, few right-hand sides)
-// take the 64 x 32 tile, everything else 64 x 64 (four waves stacked on rows).
+// Tile: 64 x 64 (four waves stacked on rows) when that grid has at least
+// four workgroups per CU; smaller grids (the solve's inverse-block products,
+// the LU's thin catch-up, deferred-row and in-block products) take 32 x 32
+// tiles for four times the workgroups.  A product in place (D = B) keeps
+// 64-row tiles so that one workgroup reads a whole column block of B before
+// writing it (callers use it with M <= 64); narrow ones (N <= 32) the 64 x 32
+// tile.
 template <typename T>
 inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
     if (g.M <= 0 || g.N <= 0 || batch <= 0 || g.inner <= 0) return HARP_OK;
@@ -302,7 +307,11 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
     const double bytes = 2.0 * sizeof(T) * nb *
                          (double(g.M) * g.K + double(g.K) * g.N + double(g.M) * g.N * (reads_c ? 2.0 : 1.0));
     const double flops = 8.0 * double(g.M) * double(g.N) * double(g.K) * nb;
-    if (g.N <= 32)
+    const int64_t wg64 = int64_t((g.M + 63) / 64) * ((g.N + 63) / 64) * batch * g.inner;
+    const bool in_place = static_cast<const void*>(g.D) == static_cast<const void*>(g.B);
+    if (!in_place && wg64 < 1024)
+        launch_cgemm<T, 32, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
+    else if (g.N <= 32)
         launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
     else
         launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream, flops, bytes);
