@@ -177,3 +177,41 @@ def test_station_gradient_matches_finite_differences(api, station, w1, w2, h):
     fd = np.array(fd)
     err = np.abs(fd - g[coords]).max() / np.abs(g).max()
     assert err <= 1e-4, (err, fd, g[coords])
+
+
+def test_large_array_gradient_matches_finite_differences(api):
+    """The large array (1024 elements, 38 m, 200 MHz, radius of influence
+    12 m, n = 8192): gradient of the pattern-spread objective with respect to
+    all 2048 coordinates through torch.autograd, against central differences
+    of the GPU forward (h = 1e-4 m) on 6 sampled coordinates."""
+    wl, models = oracle_models("cfg5")
+    model = pack(api, models[0])
+    th, ph = directions(128, seed=304)
+    tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()
+    x = torch.from_numpy(wl.x.copy()).cuda().requires_grad_(True)
+    y = torch.from_numpy(wl.y.copy()).cuda().requires_grad_(True)
+    Y, E = api.array_response(x, y, model, tht, pht, ri=wl.ri)
+    J = _objective_t(Y, E, 0.0, 1.0)
+    J.backward()
+    g = np.concatenate([x.grad.cpu().numpy(), y.grad.cpu().numpy()])
+    assert np.isfinite(g).all() and abs(g.sum()) <= 1e-6 * np.abs(g).sum()
+
+    def J_at(xv, yv):
+        with torch.no_grad():
+            Yv, Ev = api.array_response(torch.from_numpy(xv).cuda(), torch.from_numpy(yv).cuda(), model, tht, pht,
+                                        ri=wl.ri)
+            return float(_objective_t(Yv, Ev, 0.0, 1.0))
+
+    h = 1e-4
+    coords = np.random.default_rng(5).choice(2 * wl.n_ant, 6, replace=False)
+    fd = []
+    for c in coords:
+        xv, yv = wl.x.copy(), wl.y.copy()
+        v = xv if c < wl.n_ant else yv
+        v[c % wl.n_ant] += h
+        jp = J_at(xv, yv)
+        v[c % wl.n_ant] -= 2 * h
+        jm = J_at(xv, yv)
+        fd.append((jp - jm) / (2 * h))
+    err = np.abs(np.array(fd) - g[coords]).max() / np.abs(g).max()
+    assert err <= 1e-4, (err, fd, g[coords])
