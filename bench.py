@@ -171,7 +171,9 @@ def bench_batched(args, api, torch, dev):
               for f, P in zip(wl.freqs, wl.P)]
     mb = api.stack_models(models)
     layouts = batched_layouts()
-    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams)
+    # the planner's cost model measured on this GPU (one group per point)
+    cost, cost_points = api.autotune_batch_costs(mb)
+    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost)
     S.step()
     torch.cuda.synchronize()
     infos = [int(S.system(s)[2]) for s in range(S.n_systems)] + [int(S.system(s)[3])
@@ -250,6 +252,8 @@ def bench_batched(args, api, torch, dev):
             "systems": S.n_systems, "groups": [(len(g.members), g.n) for g in S.groups],
             "streams": args.streams, "refine_tol": args.tol,
             "padded_over_real_entries": padded / entries,
+            "plan_cost_model": {"t_group_s": cost[0], "t_order_s": cost[1], "t_system_s": cost[2],
+                                "measured": cost_points},
         },
         "reduced_z_entries_per_s": entries / (ms * 1e-3),
         "accuracy": {"max_rel_err_X_vs_plain": rel_x, "max_rel_err_Y_vs_plain": rel_y,

@@ -12,6 +12,7 @@ from __future__ import annotations
 import ctypes
 import math
 import struct
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -506,7 +507,7 @@ __all__ = [
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
     "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
-    "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "harp_fill_systems", "harp_port_rhs_systems",
+    "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "autotune_batch_costs", "harp_fill_systems", "harp_port_rhs_systems",
     "harp_port_admittance_systems", "BatchSolver", "StationSolver", "Cell", "harp_tessellate",
     "TessellatedSolver",
 ]
@@ -713,6 +714,48 @@ class _Group:
         self.aux, self.aux_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
         check(lib().reduced_solve_ws(n, npp, c, C64, 1, ctypes.byref(b)), "reduced_solve_ws")
         self.ws, self.ws_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
+
+
+def autotune_batch_costs(models: ModelBatch, sizes=(96, 256, 480), counts=(1, 8), reps: int = 2,
+                         seed: int = 7, tol: float = 1e-10):
+    """Measure the batch path on this GPU and fit the planner's cost model
+    t(group) = t_group + t_order N + t_system c N^3 (N = padded order, c
+    systems): one group of c systems of n_ant antennas (seeded random layouts
+    at the station density, model 0) per (n_ant, c) pair, timed over `reps`
+    passes after one warm-up, then a non-negative least-squares fit.  Returns
+    (cost triple for harp_batch_plan, the measured points)."""
+    from scipy.optimize import nnls
+    rng = np.random.default_rng(seed)
+    rows, times, points = [], [], []
+    for na in sizes:
+        # random sequential addition in a disk of the station density
+        radius = 19.0 * math.sqrt(na / 256.0)
+        pts = []
+        while len(pts) < na:
+            u, v = rng.uniform(size=2)
+            px, py = radius * math.sqrt(u) * math.cos(2 * math.pi * v), radius * math.sqrt(u) * math.sin(2 * math.pi * v)
+            if all((px - a) ** 2 + (py - b) ** 2 >= 1.5 ** 2 for a, b in pts):
+                pts.append((px, py))
+        x, y = np.array(pts).T
+        for c in counts:
+            S = BatchSolver(models, [(x, y, [0] * c)], tol=tol, streams=1, max_batch=c, pad_multiple=8,
+                            cost=[1.0, 0.0, 0.0])
+            S.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                S.step()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / reps
+            N = float(S.groups[0].n)
+            rows.append([1.0, N, c * N ** 3])
+            times.append(t)
+            points.append({"n_ant": int(na), "systems": int(c), "order": int(N), "seconds": t})
+            del S
+    A = np.array(rows)
+    scale = A.max(axis=0)
+    coef, _ = nnls(A / scale, np.array(times))
+    return [float(v) for v in coef / scale], points
 
 
 class BatchSolver:

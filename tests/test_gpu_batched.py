@@ -157,3 +157,25 @@ def test_batched_layouts_sampled_against_oracle(api, batched):
         assert _port_rel(X.cpu().numpy()[:, ports], Xo) <= 1e-6, s
         Yo = osolve.admittance(Xo, m.w, na)
         assert _rel(Y.cpu().numpy()[:, ports], Yo) <= 1e-6, s
+
+
+def test_autotuned_costs(api, small):
+    """The autotuner's fitted cost model reproduces its own measurements to a
+    factor of two and yields a valid plan; the batch solved under that plan
+    gives the same systems as under the default plan."""
+    models, layouts, mb = small
+    cost, pts = api.autotune_batch_costs(mb, sizes=(8, 24, 40), counts=(1, 4), reps=2)
+    assert len(cost) == 3 and all(c >= 0.0 for c in cost) and len(pts) == 6
+    for p in pts:
+        pred = cost[0] + cost[1] * p["order"] + cost[2] * p["systems"] * p["order"] ** 3
+        assert 0.5 * p["seconds"] <= pred <= 2.0 * p["seconds"], (p, pred)
+    A = api.BatchSolver(mb, layouts, tol=1e-10)
+    B = api.BatchSolver(mb, layouts, tol=1e-10, cost=cost)
+    A.step()
+    B.step()
+    torch.cuda.synchronize()
+    for s in range(A.n_systems):
+        xa, ya, _, _ = A.system(s)
+        xb, yb, _, _ = B.system(s)
+        assert torch.linalg.norm(xa - xb) <= 1e-9 * torch.linalg.norm(xa)
+        assert torch.linalg.norm(ya - yb) <= 1e-9 * torch.linalg.norm(ya)
