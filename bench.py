@@ -165,7 +165,7 @@ def bench_batched(args, api, torch, dev):
 
     from workloads import batched_layouts, workload
 
-    wl = workload("cfg2")        # element and frequency sweep whose models the layouts reuse
+    wl = workload("station_sweep")        # element and frequency sweep whose models the layouts reuse
     samples = api.to_device_samples(wl.elem.samples, dev)
     models = [api.harp_fit(samples, wl.elem.wire_radius, f, P, wl.Q, wl.r_min)
               for f, P in zip(wl.freqs, wl.P)]
@@ -275,7 +275,7 @@ def bench_tessellated(args, api, torch, dev):
 
     from workloads import directions, workload
 
-    wl = workload("cfg5")
+    wl = workload("large1024")
     samples = api.to_device_samples(wl.elem.samples, dev)
     model = api.harp_fit(samples, wl.elem.wire_radius, wl.freqs[0], wl.P[0], wl.Q, wl.r_min)
     mb = api.stack_models([model])
@@ -355,7 +355,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the batch of frequencies is the "
+        print(json.dumps({"error": "this benchmark runs on one GPU: the batch of frequencies is the "
                                    "unit of work and multi-GPU sharding is not implemented "
                                    "(see DESIGN.md); run with --gpus 1"}))
         sys.exit(2)
@@ -383,7 +383,7 @@ def main():
         return bench_batched(args, api, torch, dev)
     if args.workload == "tessellated":
         return bench_tessellated(args, api, torch, dev)
-    wl = workload("cfg2")
+    wl = workload("station_sweep")
     n, na, nf = wl.n, wl.n_ant, len(wl.freqs)
 
     # HARP models (built once, reused for any layout), inputs resident in HBM

@@ -119,7 +119,7 @@ def _objective_t(Y, E, w1, w2):
 def station(api):
     """The adjoint configuration: the 256-element station at 110 MHz, 1024
     directions, gradient with respect to all 512 coordinates."""
-    wl, models = oracle_models("cfg4")
+    wl, models = oracle_models("station_110mhz")
     m = models[0]
     th, ph = wl.extra["theta"], wl.extra["phi"]
     model = pack(api, m)
@@ -184,7 +184,7 @@ def test_large_array_gradient_matches_finite_differences(api):
     12 m, n = 8192): gradient of the pattern-spread objective with respect to
     all 2048 coordinates through torch.autograd, against central differences
     of the GPU forward (h = 1e-4 m) on 6 sampled coordinates."""
-    wl, models = oracle_models("cfg5")
+    wl, models = oracle_models("large1024")
     model = pack(api, models[0])
     th, ph = directions(128, seed=304)
     tht, pht = torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda()

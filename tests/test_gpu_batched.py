@@ -105,7 +105,7 @@ def test_bad_descriptor_is_reported(api, small):
 
 @pytest.fixture(scope="module")
 def batched(api):
-    wl, models = oracle_models("cfg2")
+    wl, models = oracle_models("station_sweep")
     mb = api.stack_models([pack(api, m) for m in models])
     layouts = batched_layouts()
     S = api.BatchSolver(mb, layouts, tol=1e-10, streams=2)

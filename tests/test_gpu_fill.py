@@ -30,7 +30,7 @@ def _gpu_fill(api, models_o, x, y, dtype, ri=0.0, dual=False):
     return Z.cpu().numpy(), (Z32.cpu().numpy() if Z32 is not None else None), info.cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg,P_freq", [("cfg1", None), ("cfg2", 15)])
+@pytest.mark.parametrize("cfg,P_freq", [("small16", None), ("station_sweep", 15)])
 def test_fit_matches_oracle(api, cfg, P_freq):
     wl = workload(cfg)
     i = 0 if P_freq is None else P_freq
@@ -50,8 +50,8 @@ def test_fit_matches_oracle(api, cfg, P_freq):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_fill_cfg1(api, dtype):
-    wl, models = oracle_models("cfg1")
+def test_fill_small16(api, dtype):
+    wl, models = oracle_models("small16")
     Zg, _, info = _gpu_fill(api, models, wl.x, wl.y, dtype)
     Zo = ofill.fill(models[0], wl.x, wl.y)
     eps, zero_ok, _ = block_eps(Zg[0], Zo, wl.elem.n_mbf)
@@ -67,9 +67,9 @@ def test_fill_cfg1(api, dtype):
 
 
 @pytest.mark.parametrize("mode", ["c64", "c128", "dual"])
-def test_fill_cfg2_all_frequencies(api, mode):
+def test_fill_station_sweep_all_frequencies(api, mode):
     """Full station sweep (256 elements, 8 MBFs, 16 frequencies), every block."""
-    wl, models = oracle_models("cfg2")
+    wl, models = oracle_models("station_sweep")
     dtype = "c64" if mode == "c64" else "c128"
     Zg, Z32, info = _gpu_fill(api, models, wl.x, wl.y, dtype, dual=(mode == "dual"))
     assert (info == 0).all()
@@ -134,7 +134,7 @@ def test_fill_rejects_oversized_coefficient_slab(api):
 
 
 def test_fill_counts_pairs_below_rmin(api):
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     x = wl.x.copy()
     y = wl.y.copy()
     x[5] = x[4] + 0.7          # one pair closer than r_min = 1.5 m
@@ -144,7 +144,7 @@ def test_fill_counts_pairs_below_rmin(api):
 
 
 def test_fill_rejects_mismatched_model(api):
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     mb = api.stack_models([pack(api, models[0])])
     mb.n_mbf = 3               # wrong element size for this blob
     xt = torch.from_numpy(wl.x[:10].copy()).cuda()
@@ -155,7 +155,7 @@ def test_fill_rejects_mismatched_model(api):
 
 
 def test_ports_rhs_and_admittance(api):
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     m = models[0]
     mb = api.stack_models([pack(api, m)])
     B = api.harp_port_rhs(mb, wl.n_ant)

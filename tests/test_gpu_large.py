@@ -23,7 +23,7 @@ def api():
 
 @pytest.fixture(scope="module")
 def large(api):
-    wl, models = oracle_models("cfg5")
+    wl, models = oracle_models("large1024")
     m = models[0]
     mb = api.stack_models([pack(api, m)])
     xt = torch.from_numpy(wl.x).cuda()

@@ -29,7 +29,7 @@ def _run(api, m, wl, X, th, ph):
 
 
 def test_patterns_small_array(api):
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     m = models[0]
     X = osolve.solve(ofill.fill(m, wl.x, wl.y), osolve.port_rhs(m.w, wl.n_ant))
     th, ph = directions(37, seed=5)
@@ -42,7 +42,7 @@ def test_patterns_small_array(api):
 def test_patterns_station_all_ports(api):
     """256 elements x 8 MBFs, 256 ports, 1024 directions (the adjoint
     configuration's pattern set)."""
-    wl = workload("cfg4")
+    wl = workload("station_110mhz")
     from oracle import fit as ofit
     m = ofit.fit(wl.freqs[0], wl.elem.samples, wl.P[0], wl.Q, wl.r_min,
                  wire_radius=wl.elem.wire_radius)

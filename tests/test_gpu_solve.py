@@ -173,17 +173,17 @@ def _check_against_oracle(wl, models, X, Y, tol):
 
 
 @pytest.mark.parametrize("refined", [True, False])
-def test_hot_path_cfg1(api, refined):
-    wl, models = oracle_models("cfg1")
+def test_hot_path_small16(api, refined):
+    wl, models = oracle_models("small16")
     X, Y, rep = _pipeline(api, models, wl.x, wl.y, refined)
     _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
 
 
 @pytest.mark.parametrize("refined", [True, False])
-def test_hot_path_cfg2_all_frequencies(api, refined):
+def test_hot_path_station_sweep_all_frequencies(api, refined):
     """The benchmark's configuration: 256 elements x 8 MBFs (n = 2048), 256
     ports, 16 frequencies in one batch; every frequency vs the oracle."""
-    wl, models = oracle_models("cfg2")
+    wl, models = oracle_models("station_sweep")
     X, Y, rep = _pipeline(api, models, wl.x, wl.y, refined)
     _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
     if refined:
@@ -192,8 +192,8 @@ def test_hot_path_cfg2_all_frequencies(api, refined):
 
 def test_hot_path_strong_coupling(api):
     """Larger self-block regularisation: off-diagonal blocks ~ 1/4 of the
-    diagonal, so the solve depends on the coupling (cfg1 element, a_w = 0.3)."""
-    wl, models = oracle_models("cfg1", wire_radius=0.3)
+    diagonal, so the solve depends on the coupling (16-element array's element, a_w = 0.3)."""
+    wl, models = oracle_models("small16", wire_radius=0.3)
     for refined in (True, False):
         X, Y, _ = _pipeline(api, models, wl.x, wl.y, refined)
         _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)

@@ -25,7 +25,7 @@ def api():
 
 @pytest.fixture(scope="module")
 def large(api):
-    wl, models = oracle_models("cfg5")
+    wl, models = oracle_models("large1024")
     m = models[0]
     model = pack(api, m)
     mb = api.stack_models([model])

@@ -13,7 +13,7 @@ from parity import oracle_models
 
 @pytest.fixture(scope="module")
 def small():
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     th, ph = directions(48, seed=7)
     return wl, models[0], th, ph
 

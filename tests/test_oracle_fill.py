@@ -47,7 +47,7 @@ def test_harmonic_laplace_property():
     """In the modified plane (X, Y) = t (cos alpha, sin alpha) the model term
     t^q e^{j p alpha} has Laplacian (q^2 - p^2) t^(q-2) e^{j p alpha}; a 5-point
     stencil of the phase-stripped fill reproduces it."""
-    wl = workload("cfg1")
+    wl = workload("small16")
     m = _phase_free(fit.fit(wl.freqs[0], wl.elem.samples, 6, 6, wl.r_min))
     P, Q = m.P, m.Q
     p = np.arange(-P, P + 1)[:, None]
@@ -80,13 +80,13 @@ def test_mean_value_property_of_harmonic_terms():
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    wl = workload("cfg1")
+def small16():
+    wl = workload("small16")
     return wl, fit.fit(wl.freqs[0], wl.elem.samples, 6, 6, wl.r_min)
 
 
-def test_fill_reciprocity_and_self_blocks(cfg1):
-    wl, m = cfg1
+def test_fill_reciprocity_and_self_blocks(small16):
+    wl, m = small16
     Z = fill.fill(m, wl.x, wl.y)
     assert np.abs(Z - Z.T).max() <= 1e-13 * np.abs(Z).max()
     nm = m.n_mbf
@@ -99,8 +99,8 @@ def test_fill_reciprocity_and_self_blocks(cfg1):
     assert np.abs(Z[a * nm:(a + 1) * nm, b * nm:(b + 1) * nm] - blk).max() <= 1e-14 * np.abs(blk).max()
 
 
-def test_radius_of_influence_zeroes_far_blocks(cfg1):
-    wl, m = cfg1
+def test_radius_of_influence_zeroes_far_blocks(small16):
+    wl, m = small16
     ri = 5.0
     Z = fill.fill(m, wl.x, wl.y, ri=ri)
     Zf = fill.fill(m, wl.x, wl.y)
@@ -115,11 +115,11 @@ def test_radius_of_influence_zeroes_far_blocks(cfg1):
                 assert np.array_equal(blk, Zf[a * nm:(a + 1) * nm, b * nm:(b + 1) * nm])
 
 
-def test_hybrid_fill_close_to_brute_force(cfg1):
+def test_hybrid_fill_close_to_brute_force(small16):
     """Model accuracy on the 16-element system (synthetic analogue of the
     paper's 16-element testbed check against brute-force MoM): off-diagonal
     blocks within 1e-2 of the exact reactions (reported, not a parity gate)."""
-    wl, m = cfg1
+    wl, m = small16
     Z = fill.fill(m, wl.x, wl.y)
     nm = m.n_mbf
     num = den = 0.0

@@ -105,8 +105,8 @@ def test_far_field_fourier_expansion():
     assert np.abs(series - G).max() < 1e-8 * np.abs(G).max()
 
 
-def test_cfg1_fit_is_deterministic():
-    wl = workload("cfg1")
+def test_small16_fit_is_deterministic():
+    wl = workload("small16")
     m1 = fit.fit(wl.freqs[0], wl.elem.samples, 6, 6, wl.r_min)
     m2 = fit.fit(wl.freqs[0], wl.elem.samples, 6, 6, wl.r_min)
     assert np.array_equal(m1.C, m2.C)

@@ -32,15 +32,15 @@ def test_plain_lu_matches_lapack_pivots_and_solution():
 
 
 @pytest.fixture(scope="module")
-def cfg1_system():
-    wl = workload("cfg1")
+def small16_system():
+    wl = workload("small16")
     m = fit.fit(wl.freqs[0], wl.elem.samples, 6, 6, wl.r_min)
     Z = fill.fill(m, wl.x, wl.y)
     return wl, m, Z
 
 
-def test_backward_error_and_recovery(cfg1_system):
-    _, _, Z = cfg1_system
+def test_backward_error_and_recovery(small16_system):
+    _, _, Z = small16_system
     n = Z.shape[0]
     Xt = _rand_complex(n, 7, 3)
     B = Z @ Xt
@@ -60,8 +60,8 @@ def test_port_rhs_layout():
         assert np.array_equal(B[:, j], col)
 
 
-def test_admittance_symmetric_and_single_element(cfg1_system):
-    wl, m, Z = cfg1_system
+def test_admittance_symmetric_and_single_element(small16_system):
+    wl, m, Z = small16_system
     B = solve.port_rhs(m.w, wl.n_ant)
     X = solve.solve(Z, B)
     Y = solve.admittance(X, m.w, wl.n_ant)
@@ -115,12 +115,12 @@ def test_pattern_is_far_limit_of_the_radiated_field():
     assert errs[-1] < 1e-3 * np.abs(E).max()
 
 
-def test_paper_accuracy_bound_on_16_element_array(cfg1_system):
+def test_paper_accuracy_bound_on_16_element_array(small16_system):
     """Section III-B: on a 16-element array the EEPs of the HARP solution
     differ from those of the brute-force solution by less than -30 dB
     (Eq. 8, normalised to the isolated-pattern maximum)."""
     gold = json.load(open(os.path.join(GOLDEN, "paper_eep_accuracy.json")))
-    wl, m, Z = cfg1_system
+    wl, m, Z = small16_system
     nm = m.n_mbf
     Zb = Z.copy()
     for a in range(wl.n_ant):

@@ -51,7 +51,7 @@ def test_lattice_layout_neighbours(r_ext, expect):
 
 
 def test_every_antenna_in_exactly_one_inner_part():
-    wl = workload("cfg5")
+    wl = workload("large1024")
     for r_ext in (0.0, 6.0):
         cells = ot.tessellate(wl.x, wl.y, 6.0, r_ext)
         inner = np.concatenate([m[:ni] for _, m, ni in cells])
@@ -65,7 +65,7 @@ def test_every_antenna_in_exactly_one_inner_part():
 def test_whole_array_limit_equals_full_solve():
     """With the outer hexagon covering the whole array every subarray is the
     array: X, Y and the patterns are those of the full solve."""
-    wl, models = oracle_models("cfg1")
+    wl, models = oracle_models("small16")
     m = models[0]
     th, ph = directions(40, seed=3)
     res, E = ot.solve_tessellated(m, wl.x, wl.y, 2.0, 100.0, th, ph)
@@ -110,7 +110,7 @@ def api():
 
 @pytest.mark.parametrize("r_in,r_ext", [(6.0, 0.0), (6.0, 6.0), (10.0, 5.0), (4.0, 12.0), (3.0, 100.0)])
 def test_library_tessellation_matches_oracle(api, r_in, r_ext):
-    wl = workload("cfg5")
+    wl = workload("large1024")
     a = api.harp_tessellate(wl.x, wl.y, r_in, r_ext, origin=(0.3, -1.1))
     b = ot.tessellate(wl.x, wl.y, r_in, r_ext, origin=(0.3, -1.1))
     assert len(a) == len(b)

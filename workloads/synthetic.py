@@ -32,7 +32,7 @@ _C0 = 299_792_458.0
 
 SAMPLE_FIELDS = 8  # x, y, z, ux, uy, uz, a_re, a_im
 
-CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4", "cfg5")
+CONFIG_NAMES = ("small16", "station_sweep", "batched_layouts", "station_110mhz", "large1024")
 
 
 @dataclass
@@ -151,12 +151,12 @@ def workload(name: str, n_freq: int | None = None) -> Workload:
     batched layouts, adjoint station, large array with a radius of influence).
 
     n_freq truncates a frequency sweep (used for fast test variants)."""
-    if name == "cfg1":
+    if name == "small16":
         x, y = layout_disk(16, 6.0, 1.5, seed=101)
         el = element(4, 32, seed=201)
         freqs = np.array([100e6])
         return Workload(name, x, y, el, freqs, [6], 6, 1.5)
-    if name == "cfg2":
+    if name == "station_sweep":
         x, y = layout_disk(256, 19.0, 1.5, seed=102)
         el = element(8, 64, seed=202)
         freqs = CFG2_FREQS.copy()
@@ -164,20 +164,20 @@ def workload(name: str, n_freq: int | None = None) -> Workload:
             idx = np.linspace(0, len(freqs) - 1, n_freq).round().astype(int)
             freqs = freqs[idx]
         return Workload(name, x, y, el, freqs, [harp_orders(f)[0] for f in freqs], 6, 1.5)
-    if name == "cfg4":
+    if name == "station_110mhz":
         x, y = layout_disk(256, 19.0, 1.5, seed=102)
         el = element(8, 64, seed=202)
         th, ph = directions(1024, seed=304)
         f = 110e6
         return Workload(name, x, y, el, np.array([f]), [harp_orders(f)[0]], 6, 1.5,
                         extra={"theta": th, "phi": ph, "fd_step": 1e-4})
-    if name == "cfg5":
+    if name == "large1024":
         x, y = layout_disk(1024, 38.0, 1.5, seed=105)
         el = element(8, 64, seed=202)
         f = 200e6
         return Workload(name, x, y, el, np.array([f]), [harp_orders(f)[0]], 6, 1.5, ri=12.0)
-    if name == "cfg3":
-        raise ValueError("cfg3 is a batch of layouts: use batched_layouts()")
+    if name == "batched_layouts":
+        raise ValueError("batched_layouts is a batch of layouts: use batched_layouts()")
     raise KeyError(name)
 
 
