@@ -183,6 +183,19 @@ if os.path.exists(mf):
                    f"MFMA busy over the traced duration {100 * util:5.1f} %")
         if kc in traffic:
             traffic[kc]["hw_mfma_flops_per_dispatch"] = fl
+# achieved HBM bandwidth per class: counter bytes per launch over the traced
+# average launch duration, against the 8 TB/s peak
+if traffic:
+    out.append("")
+    out.append("HBM bandwidth per class (counter bytes per launch / traced average launch; peak 8000 GB/s):")
+    for kc in sorted(traffic):
+        if not cls.get(kc):
+            continue
+        dur = sum(cls[kc]) / len(cls[kc]) * 1e-6
+        gbs = traffic[kc]["hbm_bytes_per_launch"] / dur / 1e9
+        out.append(f"  {kc:10s} {traffic[kc]['hbm_bytes_per_launch'] / 1e6:10.2f} MB per launch in "
+                   f"{dur * 1e3:8.4f} ms -> {gbs:8.1f} GB/s ({100 * gbs / 8000:5.1f} % of peak)")
+        traffic[kc]["achieved_gbs"] = gbs
 def bench_line(j, what):
     rf = j.get("roofline", {})
     out.append(f"  {what}: ms_per_step {j.get('ms_per_step'):.3f}  dominant class {rf.get('kernel')}  "
