@@ -230,13 +230,16 @@ harp_status harp_tessellate(const double *x, const double *y, int32_t n_ant, dou
 /* ------------------------------------------------------------------------ */
 
 /* Unit-voltage excitation of every port: B = I_{n_ant} (x) w, complex128
- * n x n_ant per frequency (column j holds w on the rows of antenna j). */
+ * n x n_ant per frequency (column j holds w on the rows of antenna j).
+ * Asynchronous. */
 harp_status harp_port_rhs(const void *d_models, int64_t model_stride, int32_t n_freq,
                           int32_t n_mbf, int32_t n_ant, void *d_B, int64_t ldb, int64_t stride_b,
                           hipStream_t stream);
 
 /* Port admittances Y = W^T X (complex128, n_ant x n_ant per frequency):
- * Y_ij is the current at port i for a unit voltage at port j. */
+ * Y_ij is the current at port i for a unit voltage at port j.  X is
+ * complex128 n x n_ant (ldx, stride_x).  n_mbf <= 64 (HARP_E_ARG
+ * otherwise).  Asynchronous. */
 harp_status harp_port_admittance(const void *d_models, int64_t model_stride, int32_t n_freq,
                                  int32_t n_mbf, int32_t n_ant, const void *d_X, int64_t ldx,
                                  int64_t stride_x, void *d_Y, int64_t ldy, int64_t stride_y,
