@@ -75,3 +75,22 @@ def test_argument_errors_are_synchronous(L):
                       None) == HARP_E_WORKSPACE
     ws = ctypes.c_size_t()
     assert L.harp_fit_ws(4, 32, 6, 6, 28, 14, ctypes.byref(ws)) == 0 and ws.value > 0
+
+
+def test_new_entry_points_reject_bad_arguments_synchronously(L):
+    """Batch, port and fill limits are checked on the host before anything is
+    enqueued (placeholder pointers are never dereferenced)."""
+    HARP_E_ARG = -1
+    # systems without descriptors
+    assert L.harp_fill_systems(1, 256, 1, 8, 6, 12, 1, 1, 16, None, 1, 2, 0.0, 1, 1, 16, 256, None, 0, 0, 1,
+                               None) == HARP_E_ARG
+    assert L.harp_port_rhs_systems(1, 256, 1, 8, None, 1, 2, 2, 1, 16, 32, None) == HARP_E_ARG
+    assert L.harp_port_admittance_systems(1, 256, 1, 8, None, 1, 2, 2, 1, 16, 32, 1, 2, 4, None) == HARP_E_ARG
+    # more than 64 MBFs
+    assert L.harp_fill(1, 256, 1, 65, 6, 12, 1, 1, 2, 0.0, 1, 1, 130, 0, None, 0, 0, 1, None) == HARP_E_ARG
+    assert L.harp_port_admittance(1, 256, 1, 65, 2, 1, 130, 260, 1, 2, 4, None) == HARP_E_ARG
+    # coefficients of one source MBF beyond 64 KB (64 MBFs, p_max 8, Q 6, complex128)
+    assert L.harp_fill(1, 256, 1, 64, 6, 8, 1, 1, 2, 0.0, 1, 1, 128, 0, None, 0, 0, 1, None) == HARP_E_ARG
+    # ports beyond the padded port count are refused by the kernels' descriptors,
+    # a zero port count by the host
+    assert L.harp_port_rhs_systems(1, 256, 1, 8, 1, 1, 2, 0, 1, 16, 0, None) == HARP_E_ARG

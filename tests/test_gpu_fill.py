@@ -117,6 +117,24 @@ def test_fill_lane_layouts(api, n_mbf, n_ant):
             assert zero_ok and info[0] == 0
 
 
+@pytest.mark.parametrize("n_ant", [1, 2])
+def test_fill_one_and_two_antennas(api, n_ant):
+    """Degenerate layouts: one antenna (the self block only) and a single pair."""
+    wl, models = oracle_models("small16")
+    x, y = wl.x[:n_ant].copy(), wl.y[:n_ant].copy()
+    Zo = ofill.fill(models[0], x, y)
+    for dtype in ("c128", "c64"):
+        Zg, _, info = _gpu_fill(api, models, x, y, dtype)
+        assert info[0] == 0
+        nm = models[0].n_mbf
+        for a in range(n_ant):
+            blk = slice(a * nm, (a + 1) * nm)
+            assert np.array_equal(Zg[0][blk, blk], Zo[blk, blk].astype(Zg.dtype))
+        if n_ant == 2:
+            eps, zero_ok, _ = block_eps(Zg[0], Zo, nm)
+            assert eps <= FILL_TOL[dtype] and zero_ok
+
+
 def test_fill_rejects_oversized_coefficient_slab(api):
     """The coefficients of one source MBF (all testing MBFs, all p, q) must fit
     the 64 KB staging area: a synthetic blob of 64 MBFs with P = 8, Q = 6
