@@ -347,7 +347,7 @@ def main():
                          "subarrays against its full solve")
     ap.add_argument("--r-in", type=float, default=6.0, help="tessellation inner radius (m)")
     ap.add_argument("--r-ext", type=float, default=6.0, help="tessellation extension (m)")
-    ap.add_argument("--streams", type=int, default=2, help="HIP streams of the batched workload")
+    ap.add_argument("--streams", type=int, default=4, help="HIP streams of the batched and tessellated workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference kernel that "
                          "scales the HBM byte counters) and exit")
