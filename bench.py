@@ -51,6 +51,7 @@ KERNEL_SOURCES = {
     "gemm_c64": ["paper_1702_03781_amd/csrc/cgemm.hpp", "paper_1702_03781_amd/csrc/lu.hip"],
     "gemm_c128": ["paper_1702_03781_amd/csrc/cgemm.hpp", "paper_1702_03781_amd/csrc/lu.hip"],
     "fill": ["paper_1702_03781_amd/csrc/fill.hip"],
+    "rank_update": ["paper_1702_03781_amd/csrc/lu.hip"],
 }
 
 
@@ -120,7 +121,7 @@ def roofline_from_prof(prof, steps):
     """Roofline of the kernel class with the largest summed time, from the
     library's dispatch-attached kernel timers."""
     cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
-                                                    "trsm_lower", "trsm_upper")}
+                                                    "trsm_lower", "trsm_upper", "rank_update")}
     dom = max(cand, key=lambda k: cand[k]["ms"])
     pd = prof[dom]
     avg_ms = pd["ms"] / max(1, pd["launches"])
@@ -132,6 +133,9 @@ def roofline_from_prof(prof, steps):
         peak = PEAK["fp32_mfma_tflops"] if dom == "gemm_c64" else PEAK["fp64_mfma_tflops"]
         unit = "TFLOP/s"
         achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
+    elif dom == "rank_update":
+        bound, peak, unit = "hbm", PEAK["hbm_gbs"], "GB/s"
+        achieved = pd["bytes"] / (pd["ms"] * 1e-3) / 1e9
     else:
         bound, peak, unit, achieved = "latency", None, "TFLOP/s", None
     traffic = None

@@ -61,6 +61,8 @@ def kclass(nm):
         return "getf2"
     if s.startswith("laswp_kernel"):
         return "trsm_lower"
+    if s.startswith("rank_update_kernel"):
+        return "rank_update"
     if s.startswith("fill_kernel"):
         return "fill"
     return None

@@ -10,7 +10,9 @@
  * use under stream capture; not thread-safe (one profiling thread).
  *
  * Algorithmic work per launch: complex GEMM 8 M N K flops (per matrix of the
- * batch that is active); fill 8 / 16 / 24 bytes written per entry (complex64
+ * batch that is active); rank-w update 8 M N w flops and the bytes of one
+ * read and one write of the updated block plus one read of its two factors;
+ * fill 8 / 16 / 24 bytes written per entry (complex64
  * / complex128 / both) and 0 flops (its flops, (2P+1)(2Q+4) * 2 per
  * model-evaluated entry, depend on each model's order, which the caller
  * knows); other classes report 0.
@@ -32,7 +34,8 @@ typedef enum {
     HARP_K_GEMM32 = 4,    /* complex64 MFMA GEMM */
     HARP_K_GEMM64 = 5,    /* complex128 MFMA GEMM */
     HARP_K_AUX = 6,       /* conversions, norms, axpy, ports, info reset */
-    HARP_K_COUNT = 7
+    HARP_K_RANK = 7,      /* rank-w update of an outer block after a panel */
+    HARP_K_COUNT = 8
 } harp_kernel_class;
 
 /* on != 0: clear the records and start recording; on == 0: stop. */

@@ -965,7 +965,7 @@ def prof_enable(on: bool) -> None:
     check(lib().harp_prof_enable(1 if on else 0), "harp_prof_enable")
 
 
-PROF_CLASSES = ["fill", "getf2", "trsm_lower", "trsm_upper", "gemm_c64", "gemm_c128", "aux"]
+PROF_CLASSES = ["fill", "getf2", "trsm_lower", "trsm_upper", "gemm_c64", "gemm_c128", "aux", "rank_update"]
 
 
 def prof_read() -> dict:

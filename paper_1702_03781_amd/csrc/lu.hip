@@ -626,6 +626,71 @@ __global__ void __launch_bounds__(256) laswp_kernel(LaswpArgs la) {
 }
 
 // ---------------------------------------------------------------------------
+// Update of the rest of an outer block after one of its panels:
+//   A[j0+w:n, j0+w:c_end) -= A[j0+w:n, j0:j0+w) A[j0:j0+w, j0+w:c_end),  w <= W.
+// A contraction of at most W is a few flops per byte, so this is an HBM
+// stream, not a matrix-core product: one row per thread (the column-major
+// loads and stores of a wave are 64 consecutive rows), CN columns per
+// workgroup with their W x CN block of U broadcast from LDS, and every load of
+// a thread issued before its first store.  The regions read (the panel's
+// columns, the strip's rows) and written are disjoint.
+// ---------------------------------------------------------------------------
+
+struct RankArgs {
+    void* A;
+    int64_t lda, sA;
+    int n, j0, w, c_end;
+};
+
+template <typename T, int W, int CN>
+__global__ void __launch_bounds__(256) rank_update_kernel(RankArgs ra) {
+    using V = typename C2<T>::t;
+    const int b = blockIdx.z;
+    V* A = reinterpret_cast<V*>(ra.A) + size_t(b) * ra.sA;
+    const int64_t lda = ra.lda;
+    const int j0 = ra.j0, w = ra.w, r0 = j0 + w;
+    const int cb = r0 + int(blockIdx.y) * CN;
+    const int ncol = min(CN, ra.c_end - cb);
+    const int i = r0 + int(blockIdx.x) * 256 + int(threadIdx.x);
+    __shared__ V u[W][CN];
+    if (threadIdx.x < W * CN) {
+        const int k = threadIdx.x / CN, c = threadIdx.x % CN;
+        u[k][c] = (k < w && c < ncol) ? A[size_t(cb + c) * lda + j0 + k] : V{T(0), T(0)};
+    }
+    V l[W], cv[CN];
+    const bool row = i < ra.n;
+#pragma unroll
+    for (int k = 0; k < W; ++k) l[k] = (row && k < w) ? A[size_t(j0 + k) * lda + i] : V{T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < CN; ++c) cv[c] = (row && c < ncol) ? A[size_t(cb + c) * lda + i] : V{T(0), T(0)};
+    __syncthreads();
+    if (!row) return;
+#pragma unroll
+    for (int c = 0; c < CN; ++c) {
+        if (c >= ncol) break;
+        V acc = cv[c];
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc = cfms(acc, l[k], u[k][c]);
+        A[size_t(cb + c) * lda + i] = acc;
+    }
+}
+
+template <typename T>
+harp_status launch_rank_update(void* A, int64_t lda, int64_t sA, int n, int j0, int w, int c_end, int batch,
+                               hipStream_t st) {
+    constexpr int W = 8, CN = 8;
+    const int M = n - j0 - w, N = c_end - j0 - w;
+    if (w < 1 || w > W || M <= 0 || N <= 0) return HARP_E_ARG;
+    const dim3 grid(unsigned((M + 255) / 256), unsigned((N + CN - 1) / CN), unsigned(batch));
+    const double bytes = double(batch) * double(2 * sizeof(T)) * (2.0 * M * N + double(M) * w + double(w) * N);
+    RankArgs ra{A, lda, sA, n, j0, w, c_end};
+    HARP_PROF_EXT_LAUNCH(HARP_K_RANK, st, 8.0 * double(batch) * M * N * w, bytes, (rank_update_kernel<T, W, CN>),
+                         grid, dim3(256), 0, ra);
+    HARP_LAUNCH_CHECK();
+    return HARP_OK;
+}
+
+// ---------------------------------------------------------------------------
 // inverses of the diagonal blocks (solve groups of SB rows)
 //
 // After the factorisation the unit-lower and upper SB x SB diagonal blocks of
@@ -961,9 +1026,7 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                 PanelArgs pa{A, lda, sA, n, k0, kend, j0, w, ipiv, info, (last && block_row) ? blk : nullptr};
                 if ((s = launch_getf2<T>(pa, W, batch, st)) != HARP_OK) return s;
                 if (j0 + w < kend) {
-                    GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - j0 - w, kend - j0 - w, w, j0 + w, j0, j0, j0 + w,
-                                                j0 + w, j0 + w, T(-1), T(1), nullptr);
-                    if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
+                    if ((s = launch_rank_update<T>(A, lda, sA, n, j0, w, kend, batch, st)) != HARP_OK) return s;
                 }
             }
             if (block_row) {
