@@ -163,45 +163,51 @@ __device__ inline float2 crecip_pivot(float2 a) {
 }
 __device__ inline double2 crecip_pivot(double2 a) { return crecip(a); }
 
-// Single-precision pivot search on 64-bit keys: (bits of |re|+|im|) << 32 |
-// ~row.  For non-negative floats the bit pattern orders like the value, and
-// ~row makes the smaller row win a tie, so the largest key is LAPACK's pivot.
-// Rows outside [j, n) and NaN magnitudes carry key 0 and never win; a zero
-// magnitude has a nonzero key.  One 64-bit compare per reduction step.
-__device__ inline uint64_t pivot_key(float m, int row, bool valid) {
-    return (valid && m == m) ? (uint64_t(__float_as_uint(m)) << 32) | uint32_t(~row) : uint64_t(0);
-}
-template <int CTRL, int ROWS> __device__ inline uint64_t dpp_key(uint64_t v) {
-    int lo, hi;
+// Single-precision pivot search on 32-bit keys: the bit pattern of a
+// magnitude |re| + |im| (non-negative, so its bits order like its value), or
+// -1 for rows outside [j, n) and NaN magnitudes, which then never win.  The
+// largest key comes from integer DPP max steps (one VALU operation each), the
+// lanes holding it from a ballot; only an exact tie between lanes needs a
+// second reduction, a minimum over their row labels, so the smallest row wins
+// as in LAPACK.
+template <int CTRL, int ROWS> __device__ inline int dpp_any(int v) {
     if constexpr (ROWS == 0xF) {   // every lane written: no old value needed
-        lo = __builtin_amdgcn_mov_dpp(int(v), CTRL, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_mov_dpp(int(v >> 32), CTRL, 0xF, 0xF, false);
-    } else {
-        lo = __builtin_amdgcn_update_dpp(int(v), int(v), CTRL, ROWS, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp(int(v >> 32), int(v >> 32), CTRL, ROWS, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+    } else {                       // rows left out keep their own value
+        return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
     }
-    return (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo);
 }
-template <int CTRL, int ROWS> __device__ inline void key_step(uint64_t& k) {
-    const uint64_t o = dpp_key<CTRL, ROWS>(k);
-    k = o > k ? o : k;
+template <int CTRL, int ROWS> __device__ inline void max_step(int& v) { v = max(v, dpp_any<CTRL, ROWS>(v)); }
+template <int CTRL, int ROWS> __device__ inline void min_step(int& v) { v = min(v, dpp_any<CTRL, ROWS>(v)); }
+// every lane of each 16-lane row ends with the row's maximum / minimum
+__device__ inline int row16_max(int v) {
+    max_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+    max_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+    max_step<0x124, 0xF>(v);   // row_ror:4
+    max_step<0x128, 0xF>(v);   // row_ror:8
+    return v;
 }
-__device__ inline void row16_key_max(uint64_t& k) {
-    key_step<0xB1, 0xF>(k);
-    key_step<0x4E, 0xF>(k);
-    key_step<0x124, 0xF>(k);
-    key_step<0x128, 0xF>(k);
+__device__ inline int row16_min(int v) {
+    min_step<0xB1, 0xF>(v);
+    min_step<0x4E, 0xF>(v);
+    min_step<0x124, 0xF>(v);
+    min_step<0x128, 0xF>(v);
+    return v;
 }
-__device__ inline uint64_t readlane_key(uint64_t k, int l) {
-    const int lo = __builtin_amdgcn_readlane(int(k), l), hi = __builtin_amdgcn_readlane(int(k >> 32), l);
-    return (uint64_t(uint32_t(hi)) << 32) | uint32_t(lo);
+// the wave's maximum / minimum (uniform)
+__device__ inline int wave_max(int v) {
+    v = row16_max(v);
+    max_step<0x142, 0xA>(v);   // row_bcast:15
+    max_step<0x143, 0xC>(v);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
-__device__ inline uint64_t wave_key_max(uint64_t k) {
-    row16_key_max(k);
-    key_step<0x142, 0xA>(k);   // row_bcast:15
-    key_step<0x143, 0xC>(k);   // row_bcast:31
-    return readlane_key(k, 63);
+__device__ inline int wave_min(int v) {
+    v = row16_min(v);
+    min_step<0x142, 0xA>(v);
+    min_step<0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
 }
+__device__ inline uint64_t ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 // LDS of the panel kernel (candidates double-buffered by column parity);
 // the row buffers come first so their 16-byte vectors stay aligned
@@ -211,7 +217,6 @@ template <typename T, int NT, int W> struct alignas(16) PanelShared {
     V cand_row[2][NW][W];
     V stage[NBMAX - W][2 * W];
     V Ls[W][W];
-    uint64_t cand_k[2][NW];
     T cand_v[2][NW];
     int cand_i[2][NW];
     int piv_s[W];
@@ -253,16 +258,27 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
         // wave candidate: the label of its row (-1: the wave has none)
         int bidx = -1;
         T best = T(-1);
-        uint64_t wkey = 0;
         if constexpr (sizeof(T) == 4) {
+            // lane candidate: the largest key of its rows, smallest label on a tie
+            int key = -1, lab = INT_MAX;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
-                const uint64_t k =
-                    pivot_key(fabsf(a[r][JJ].x) + fabsf(a[r][JJ].y), lrow[r], lrow[r] >= j && lrow[r] < n);
-                wkey = k > wkey ? k : wkey;
+                const float m = fabsf(a[r][JJ].x) + fabsf(a[r][JJ].y);
+                const int k = (lrow[r] >= j && lrow[r] < n && m == m) ? __float_as_int(m) : -1;
+                const bool t = (k > key) | ((k == key) & (lrow[r] < lab));
+                key = t ? k : key;
+                lab = t ? lrow[r] : lab;
             }
-            wkey = wave_key_max(wkey);
-            if (wkey != 0) bidx = int(~uint32_t(wkey));
+            const int wk = wave_max(key);
+            if (wk >= 0) {
+                const uint64_t hit = ballot64(key == wk);
+                if (__popcll(hit) == 1) {
+                    bidx = __builtin_amdgcn_readlane(lab, __ffsll(static_cast<long long>(hit)) - 1);
+                } else {
+                    bidx = wave_min(key == wk ? lab : INT_MAX);
+                }
+                best = __int_as_float(wk);
+            }
         } else {
             // rows outside [j, n) carry -2 and never win; a NaN never wins a comparison
 #pragma unroll
@@ -273,44 +289,47 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
             wave_argmax(best, bidx);
             if (!(best >= T(0))) bidx = -1;   // no qualifying row in this wave
         }
-        // the holder of the wave's candidate publishes that row
+        // the holder of the wave's candidate publishes that row (the columns
+        // from JJ on, rounded down to a 16-byte vector, are all that is read)
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (lrow[r] == bidx) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) sh.cand_row[par][wave][c] = a[r][c];
+                for (int c = (JJ / 2) * 2; c < W; ++c) sh.cand_row[par][wave][c] = a[r][c];
             }
         }
         if (lane == 0) {
-            if constexpr (sizeof(T) == 4) {
-                sh.cand_k[par][wave] = wkey;
-            } else {
-                sh.cand_v[par][wave] = bidx >= 0 ? best : T(-1);
-                sh.cand_i[par][wave] = bidx >= 0 ? bidx : INT_MAX;
-            }
+            sh.cand_v[par][wave] = bidx >= 0 ? best : T(-1);
+            sh.cand_i[par][wave] = bidx >= 0 ? bidx : INT_MAX;
         }
         __syncthreads();
         // every wave reduces the NW candidates at once (lane q holds wave q's);
         // wb is the wave that published the winner.  No qualifying row at
         // all (a NaN column) is handled like a zero pivot on row j itself.
-        int p, wb;
-        bool zero;
+        int p = j, wb = -1;
+        bool zero = true;
+        T bv = T(-1);
+        int bi = INT_MAX;
+        if (lane < NW) {
+            bv = sh.cand_v[par][lane];
+            bi = sh.cand_i[par][lane];
+        }
         if constexpr (sizeof(T) == 4) {
-            const uint64_t mine = lane < NW ? sh.cand_k[par][lane] : uint64_t(0);
-            uint64_t k = mine;
-            row16_key_max(k);
-            k = readlane_key(k, 0);
-            const uint64_t hit = __ballot(lane < NW && mine == k);
-            wb = k != 0 ? __ffsll(static_cast<long long>(hit)) - 1 : -1;
-            p = k != 0 ? int(~uint32_t(k)) : j;
-            zero = (k >> 32) == 0;
-        } else {
-            T bv = T(-1);
-            int bi = INT_MAX;
-            if (lane < NW) {
-                bv = sh.cand_v[par][lane];
-                bi = sh.cand_i[par][lane];
+            // candidates' magnitudes are non-negative or -1: their bits order as ints
+            const int ck = __float_as_int(bv);
+            const int g = __builtin_amdgcn_readlane(row16_max(ck), 0);
+            if (g >= 0) {
+                const uint64_t hit = ballot64(lane < NW && ck == g);
+                if (__popcll(hit) == 1) {
+                    wb = __ffsll(static_cast<long long>(hit)) - 1;
+                    p = __builtin_amdgcn_readlane(bi, wb);
+                } else {
+                    p = __builtin_amdgcn_readlane(row16_min(ck == g ? bi : INT_MAX), 0);
+                    wb = __ffsll(static_cast<long long>(ballot64(lane < NW && bi == p))) - 1;
+                }
+                zero = g == 0;
             }
+        } else {
             const int mine = bi;
             row16_argmax(bv, bi);
             bv = readlane_v(bv, 0);
@@ -678,14 +697,18 @@ __global__ void __launch_bounds__(256) rank_update_kernel(RankArgs ra) {
 template <typename T>
 harp_status launch_rank_update(void* A, int64_t lda, int64_t sA, int n, int j0, int w, int c_end, int batch,
                                hipStream_t st) {
-    constexpr int W = 8, CN = 8;
+    constexpr int CN = 8;
     const int M = n - j0 - w, N = c_end - j0 - w;
-    if (w < 1 || w > W || M <= 0 || N <= 0) return HARP_E_ARG;
+    if (w < 1 || w > 16 || M <= 0 || N <= 0) return HARP_E_ARG;
     const dim3 grid(unsigned((M + 255) / 256), unsigned((N + CN - 1) / CN), unsigned(batch));
     const double bytes = double(batch) * double(2 * sizeof(T)) * (2.0 * M * N + double(M) * w + double(w) * N);
+    const double flops = 8.0 * double(batch) * M * N * w;
     RankArgs ra{A, lda, sA, n, j0, w, c_end};
-    HARP_PROF_EXT_LAUNCH(HARP_K_RANK, st, 8.0 * double(batch) * M * N * w, bytes, (rank_update_kernel<T, W, CN>),
-                         grid, dim3(256), 0, ra);
+    if (w <= 8) {
+        HARP_PROF_EXT_LAUNCH(HARP_K_RANK, st, flops, bytes, (rank_update_kernel<T, 8, CN>), grid, dim3(256), 0, ra);
+    } else {
+        HARP_PROF_EXT_LAUNCH(HARP_K_RANK, st, flops, bytes, (rank_update_kernel<T, 16, CN>), grid, dim3(256), 0, ra);
+    }
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
@@ -943,18 +966,28 @@ template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
     if (pa.w > W) return HARP_E_ARG;
-    if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
-    if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
-    if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, W>(pa, batch, st);
-    if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, W>(pa, batch, st);
-    if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, W>(pa, batch, st);
-    return HARP_E_ARG;
+    if constexpr (W >= 16) {   // 1024 threads would spill a 16-column panel
+        if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
+        if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
+        if (m <= 512 * 4) return launch_getf2_cfg<T, 512, 4, W>(pa, batch, st);
+        return HARP_E_ARG;
+    } else {
+        if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
+        if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
+        if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, W>(pa, batch, st);
+        if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, W>(pa, batch, st);
+        if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, W>(pa, batch, st);
+        return HARP_E_ARG;
+    }
 }
 
 template <typename T>
 harp_status launch_getf2(const PanelArgs& pa, int W, int batch, hipStream_t st) {
     if (pa.w > W) return HARP_E_ARG;
     switch (W) {
+        case 16:
+            if constexpr (sizeof(T) == 4) return launch_getf2_w<T, 16>(pa, batch, st);
+            return HARP_E_ARG;
         case 8: return launch_getf2_w<T, 8>(pa, batch, st);
         case 4: return launch_getf2_w<T, 4>(pa, batch, st);
         case 2: return launch_getf2_w<T, 2>(pa, batch, st);

@@ -108,6 +108,46 @@ def test_pivots_follow_partial_pivoting(api):
     assert np.abs(U - np.triu(lu_ref)).max() <= 1e-11 * np.abs(lu_ref).max()
 
 
+def test_complex64_pivot_ties_take_the_smallest_row(api):
+    """Single precision, n = 2048 (one panel row per 1024-thread workgroup
+    thread and a second one 1024 rows further): exact ties of the largest
+    |Re| + |Im| in column 0 within one thread, within one wave, across waves
+    and over the whole column go to the smallest row (LAPACK's first maximum);
+    a zero or NaN column is a zero pivot on the diagonal row.  The
+    factors of the nonsingular ones solve the system (refined to FP64)."""
+    n = 2048
+    rng = np.random.default_rng(31)
+    A = 0.25 * (rng.standard_normal((6, n, n)) + 1j * rng.standard_normal((6, n, n)))
+    A[:, :, 0] *= 0.1                                  # column 0 below the ties' magnitude
+    A[0, [1724, 700], 0] = [3.0, -3.0j]                # rows 700 and 700 + 1024: same thread
+    A[1, [703, 1725, 701], 0] = [1.5 + 1.5j, -3.0, 3.0j]   # one wave, three rows
+    A[2, [2000, 1500, 900], 0] = [3.0, 2.0 - 1.0j, -1.0 + 2.0j]   # three waves
+    A[3, :, 0] = rng.choice([1, -1], n) + 1j * rng.choice([1, -1], n)   # the whole column ties
+    A[4, :, 0] = 0.0
+    A[5, :, 0] = np.nan
+    A = A.astype(np.complex64)
+    LU = _to_cm(api, A, torch.complex64)
+    F = api.reduced_factor(LU)
+    torch.cuda.synchronize()
+    piv = F.ipiv.cpu().numpy()
+    assert list(piv[:, 0]) == [700, 701, 900, 0, 0, 0], piv[:, 0]
+    assert list(F.info.cpu().numpy()) == [0, 0, 0, 0, 1, 1]
+    assert ((piv >= np.arange(n)[None]) & (piv < n)).all()
+    # each pivot has the largest |Re| + |Im| of its column at its step, so
+    # every multiplier has modulus at most sqrt(2)
+    L = np.tril(LU.cpu().numpy()[:4], -1)
+    assert np.abs(L).max() <= np.sqrt(2.0) * (1 + 1e-5)
+    Bh = _rand((6, n, 3), 32)
+    A64 = A.astype(np.complex128)
+    X, rep = api.reduced_solve(F, _to_cm(api, Bh, torch.complex128), Z64=_to_cm(api, A64, torch.complex128),
+                               tol=1e-12, max_iter=10, raise_noconv=False)
+    torch.cuda.synchronize()
+    assert all(r["converged"] for r in rep[:4]), rep
+    ref = np.linalg.solve(A64[:4], Bh[:4])
+    err = np.linalg.norm(X.cpu().numpy()[:4] - ref) / np.linalg.norm(ref)
+    assert err <= 1e-9, err
+
+
 def test_exact_zero_pivot_sets_info(api):
     n = 100
     A = _rand((2, n, n), 7)
