@@ -117,6 +117,21 @@ def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
     }
 
 
+def class_rates(prof, steps):
+    """Per kernel class: time and launches per step, and the algorithmic
+    rates its timers give (flops and bytes that the library attaches)."""
+    out = {}
+    for k, v in prof.items():
+        if v["launches"] == 0:
+            continue
+        sec = v["ms"] * 1e-3
+        out[k] = {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": v["launches"] / steps,
+                  "avg_launch_us": round(1e3 * v["ms"] / v["launches"], 2),
+                  "tflops": round(v["flops"] / sec / 1e12, 2) if v["flops"] > 0 else None,
+                  "gbs": round(v["bytes"] / sec / 1e9, 1) if v["bytes"] > 0 else None}
+    return out
+
+
 def roofline_from_prof(prof, steps):
     """Roofline of the kernel class with the largest summed time, from the
     library's dispatch-attached kernel timers."""
@@ -264,6 +279,7 @@ def bench_batched(args, api, torch, dev):
                      "all_converged": conv, "gate": REL_GATE, "ok": accuracy_ok,
                      "refine_iters": iters, "checked_systems": picks},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
+        "kernel_classes": class_rates(prof, args.steps),
         "roofline": roofline,
         "cpu_baseline": None,
     }
@@ -508,6 +524,7 @@ def main():
             "ms_per_step": ms_plain, "port_solves_per_s": port_solves / (ms_plain * 1e-3),
             "speedup_refined_over_plain": ms_plain / ms},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
+        "kernel_classes": class_rates(prof, args.steps),
         "roofline": roofline,
         "paper_context": {"fill_s": 10.0, "solve_s": 12.6, "eeps_s": 6.0,
                           "hardware": "Intel Core i7-3770 3.4 GHz (desktop)",
