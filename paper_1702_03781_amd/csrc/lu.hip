@@ -210,17 +210,20 @@ __device__ inline int wave_min(int v) {
 __device__ inline uint64_t ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 // LDS of the panel kernel (candidates double-buffered by column parity);
-// the row buffers come first so their 16-byte vectors stay aligned
-template <typename T, int NT, int W> struct alignas(16) PanelShared {
+// the row buffers come first so their 16-byte vectors stay aligned.  W is
+// the width of one register block, WT the panel's whole width (W or 2 W).
+template <typename T, int NT, int W, int WT = W> struct alignas(16) PanelShared {
     using V = typename C2<T>::t;
     static constexpr int NW = NT / 64;
     V cand_row[2][NW][W];
-    V stage[NBMAX - W][2 * W];
-    V Ls[W][W];
+    V stage[NBMAX - W][2 * WT];
+    V Ls[WT][WT];
+    V Ub[W][W];
     T cand_v[2][NW];
     int cand_i[2][NW];
-    int piv_s[W];
-    int cand_s[2 * W], src_s[2 * W];
+    int piv_s[WT];
+    int cand_s[2 * WT], src_s[2 * WT];
+    int cand2_s[2 * W], src2_s[2 * W];
 };
 
 // Columns [c_from, W) of a row held in LDS, read as 16-byte vectors
@@ -239,22 +242,23 @@ template <int W, int C_FROM> __device__ inline void lds_row(const double2* src, 
     for (int c = C_FROM; c < W; ++c) dst[c] = src[c];
 }
 
-// Column JJ of the panel (then JJ+1, ...): a compile-time recursion, so the
-// register-resident panel is only ever indexed by constants.  Row exchanges
-// are virtual: lrow[r] is the row that register row r currently holds, an
-// exchange of rows j and p swaps two of these labels, and the write-back puts
-// every register row at its label.
-template <typename T, int NT, int RPT, int W, int JJ>
+// Column JJ of a register block of the panel (then JJ+1, ...): a compile-time
+// recursion, so the register-resident panel is only ever indexed by
+// constants.  The block holds the panel's columns [C0, C0 + W).  Row
+// exchanges are virtual: lrow[r] is the row that register row r currently
+// holds, an exchange of rows j and p swaps two of these labels, and the
+// write-back puts every register row at its label.
+template <typename T, int NT, int RPT, int W, int WT, int C0, int JJ>
 __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], int (&lrow)[RPT],
-                                              PanelShared<T, NT, W>& sh, const PanelArgs& pa, int b, int tid) {
+                                              PanelShared<T, NT, W, WT>& sh, const PanelArgs& pa, int b, int tid) {
     if constexpr (JJ < W) {
         using V = typename C2<T>::t;
         constexpr int NW = NT / 64;
-        constexpr int par = JJ & 1;
+        constexpr int par = (C0 + JJ) & 1;
         const int n = pa.n;
-        if (JJ >= pa.w) return;
+        if (C0 + JJ >= pa.w) return;
         const int lane = tid & 63, wave = tid >> 6;
-        const int j = pa.j0 + JJ;
+        const int j = pa.j0 + C0 + JJ;
         // wave candidate: the label of its row (-1: the wave has none)
         int bidx = -1;
         T best = T(-1);
@@ -340,7 +344,7 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
             p = bv >= T(0) ? bi : j;
         }
         if (tid == 0) {
-            sh.piv_s[JJ] = p;
+            sh.piv_s[C0 + JJ] = p;
             pa.ipiv[size_t(b) * n + j] = p;
             if (zero) atomicCAS(pa.info + b, 0, j + 1);
         }
@@ -371,7 +375,7 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
 #pragma unroll
             for (int r = 0; r < RPT; ++r) a[r][c] = cfms(a[r][c], l[r], prow[c]);
         }
-        panel_columns<T, NT, RPT, W, JJ + 1>(a, lrow, sh, pa, b, tid);
+        panel_columns<T, NT, RPT, W, WT, C0, JJ + 1>(a, lrow, sh, pa, b, tid);
     }
 }
 
@@ -481,29 +485,40 @@ __device__ void block_finish(const PanelArgs& pa, int b, int tid, BlkShared<T>& 
 }
 
 // One workgroup per matrix factors rows [j0, n) x columns [j0, j0+w) held in
-// registers (thread t starts with rows j0 + t + r NT).  One barrier per
-// column: each wave publishes its best candidate together with that row;
-// after the barrier every thread picks the winner, the labels of rows j and
-// p are exchanged (no data moves), and all threads scale and update.
-template <typename T, int NT, int RPT, int W>
+// registers (thread t starts with rows j0 + t + r NT), in H register blocks of
+// W columns (w <= H W).  One barrier per column: each wave publishes its best
+// candidate together with that row; after the barrier every thread picks the
+// winner, the labels of rows j and p are exchanged (no data moves), and all
+// threads scale and update.  With two blocks, the second block is loaded
+// with the first and, once the first is factored, updated inside the
+// workgroup: its rows at the first block's pivot labels are solved with the
+// first block's unit-lower top (giving U), every row below subtracts its
+// multipliers times U, and the second block is factored like the first.
+// One launch then covers 2 W columns, and the outer block's remaining columns
+// take one update per 2 W columns.
+template <typename T, int NT, int RPT, int W, int H>
 __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     using V = typename C2<T>::t;
     constexpr int NW = NT / 64;
+    constexpr int WT = W * H;
     static_assert(NW <= 16, "candidates are reduced within one 16-lane row");
+    static_assert(H == 1 || H == 2, "one or two register blocks");
+    static_assert(2 * WT + 2 * W <= NT, "one thread per row of the exchange maps");
     const int b = blockIdx.x;
     V* A = reinterpret_cast<V*>(pa.A) + size_t(b) * pa.sA;
     const int64_t lda = pa.lda;
     const int n = pa.n, j0 = pa.j0, w = pa.w;
     const int tid = threadIdx.x;
 
-    __shared__ PanelShared<T, NT, W> sh;
+    __shared__ PanelShared<T, NT, W, WT> sh;
     auto& Ls = sh.Ls;
     auto& piv_s = sh.piv_s;
     auto& cand_s = sh.cand_s;
     auto& src_s = sh.src_s;
     auto& stage = sh.stage;
 
-    V a[RPT][W];
+    constexpr int W2 = H == 2 ? W : 1;   // second block (unused when H == 1)
+    V a[RPT][W], a2[RPT][W2];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = j0 + tid + r * NT;
@@ -515,26 +530,110 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     int lrow[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) lrow[r] = j0 + tid + r * NT;
-    panel_columns<T, NT, RPT, W, 0>(a, lrow, sh, pa, b, tid);
-    __syncthreads();
+    panel_columns<T, NT, RPT, W, WT, 0, 0>(a, lrow, sh, pa, b, tid);
+    const int w1 = w < W ? w : W;   // columns of the first block
+    const int w2 = w - w1;          // columns of the second (0 with one block)
 
-    // write every register row back at its label; keep the unit-lower top
-    // block in LDS
+    // the first block goes back at its labels now (with two blocks the
+    // second block's exchanges reach it below, like any other column); its
+    // unit-lower top stays in LDS
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = lrow[r];
         if (row < n) {
 #pragma unroll
             for (int c = 0; c < W; ++c)
-                if (c < w) A[size_t(j0 + c) * lda + row] = a[r][c];
+                if (c < w1) A[size_t(j0 + c) * lda + row] = a[r][c];
         }
-        if (row >= j0 && row < j0 + w) {
+        if (row >= j0 && row < j0 + w1) {
 #pragma unroll
             for (int c = 0; c < W; ++c) Ls[row - j0][c] = a[r][c];
         }
     }
+    if constexpr (H == 2) {
+        if (w2 > 0) {
+            // the second block, loaded once the first is factored (holding it
+            // through the first block's columns would cost 32 more registers)
+            // and its rows at the first block's top labels (the first
+            // block's exchanges are label swaps only)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = j0 + tid + r * NT;
+#pragma unroll
+                for (int c = 0; c < W; ++c)
+                    a2[r][c] = (row < n && c < w2) ? A[size_t(j0 + W + c) * lda + row] : V{T(0), T(0)};
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = lrow[r];
+                if (row >= j0 && row < j0 + W) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) sh.Ub[row - j0][c] = a2[r][c];
+                }
+            }
+            __syncthreads();
+            // U = L11^-1 (those rows): one column per thread
+            if (tid < W) {
+                V x[W];
+#pragma unroll
+                for (int i = 0; i < W; ++i) x[i] = sh.Ub[i][tid];
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+#pragma unroll
+                    for (int i = q + 1; i < W; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
+                }
+#pragma unroll
+                for (int i = 0; i < W; ++i) sh.Ub[i][tid] = x[i];
+            }
+            __syncthreads();
+            // rows below the first block: a2 -= L U, one row of U at a time
+            // (the compiler fence keeps all 64 entries of U from being loaded
+            // into registers at once); the top rows of a2 become U
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                V u[W];
+#pragma unroll
+                for (int c = 0; c < W; ++c) u[c] = sh.Ub[k][c];
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    if (lrow[r] >= j0 + W) {
+#pragma unroll
+                        for (int c = 0; c < W; ++c) a2[r][c] = cfms(a2[r][c], a[r][k], u[c]);
+                    }
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = lrow[r];
+                if (row >= j0 && row < j0 + W) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) a2[r][c] = sh.Ub[row - j0][c];
+                }
+            }
+            panel_columns<T, NT, RPT, W, WT, W2, 0>(a2, lrow, sh, pa, b, tid);
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = lrow[r];
+                if (row < n) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c)
+                        if (c < w2) A[size_t(j0 + W + c) * lda + row] = a2[r][c];
+                }
+                if (row >= j0 && row < j0 + w) {
+#pragma unroll
+                    for (int c = 0; c < W; ++c) Ls[row - j0][W + c] = a2[r][c];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
     // rows touched by this panel's exchanges: the w top rows and the w pivot
-    // rows; source of each after all exchanges, by walking them backwards
+    // rows; source of each after all exchanges, by walking them backwards.
+    // With two blocks, the first block's columns take the second block's
+    // exchanges only (map 2: its w2 top rows and w2 pivot rows).
     if (tid < 2 * w) {
         const int r = tid < w ? j0 + tid : piv_s[tid - w];
         int src = r;
@@ -544,18 +643,33 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
         }
         cand_s[tid] = r;
         src_s[tid] = src;
+    } else if (tid < 2 * w + 2 * w2) {
+        const int t = tid - 2 * w;
+        const int r = t < w2 ? j0 + W + t : piv_s[W + t - w2];
+        int src = r;
+        for (int q = w - 1; q >= W; --q) {
+            if (src == j0 + q) src = piv_s[q];
+            else if (src == piv_s[q]) src = j0 + q;
+        }
+        sh.cand2_s[t] = r;
+        sh.src2_s[t] = src;
     }
     __syncthreads();
 
-    // other columns of the outer block: gather the exchanged rows through LDS
+    // other columns of the outer block (then, with two blocks, the first
+    // block's columns): gather the exchanged rows through LDS
     const int left = j0 - pa.k0;
     const int right = pa.kend - (j0 + w);
     const int nother = left + right;
-    const int n2 = 2 * w;
+    const int n2 = 2 * w, m2 = 2 * w2;
     for (int e = tid; e < n2 * nother; e += NT) {
         const int t = e % n2, oc = e / n2;
         const int col = oc < left ? pa.k0 + oc : j0 + w + (oc - left);
         stage[oc][t] = A[size_t(col) * lda + src_s[t]];
+    }
+    for (int e = tid; e < m2 * W; e += NT) {
+        const int t = e % m2, c = e / m2;
+        stage[nother + c][t] = A[size_t(j0 + c) * lda + sh.src2_s[t]];
     }
     __syncthreads();
     for (int e = tid; e < n2 * nother; e += NT) {
@@ -567,21 +681,31 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
         if (is_right && r < j0 + w) continue;
         A[size_t(col) * lda + r] = stage[oc][t];
     }
+    for (int e = tid; e < m2 * W; e += NT) {
+        const int t = e % m2, c = e / m2;
+        const int r = sh.cand2_s[t];
+        A[size_t(j0 + c) * lda + r] = stage[nother + c][t];
+        // the second block's top rows: their first-block multipliers
+        if (t < w2) Ls[W + t][c] = stage[nother + c][t];
+    }
+    __syncthreads();
     // unit-lower solve of the top rows of the right columns
     // (one column per thread: the outer block is narrower than the workgroup,
     // and a single pass keeps the LDS reads of Ls out of any loop)
     static_assert(NBMAX <= NT, "one thread per column of the outer block");
     if (const int oc = left + tid; oc < nother) {
         const int col = j0 + w + (oc - left);
-        V x[W];
+        V x[WT];
 #pragma unroll
-        for (int i = 0; i < W; ++i) x[i] = i < w ? stage[oc][i] : V{T(0), T(0)};
-        // column-oriented substitution: x[q] is final once reached
+        for (int i = 0; i < WT; ++i) x[i] = i < w ? stage[oc][i] : V{T(0), T(0)};
+        // column-oriented substitution: x[q] is final once reached (the
+        // compiler fence keeps the reads of L to one column at a time)
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
+        for (int q = 0; q < WT; ++q) {
             if (q < w) A[size_t(col) * lda + j0 + q] = x[q];
 #pragma unroll
-            for (int i = q + 1; i < W; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
+            for (int i = q + 1; i < WT; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
     }
     if (pa.blk) {
@@ -936,9 +1060,10 @@ template <typename T> struct LuCfg {
 
 // Panel width: the register-resident panel holds RPT x W complex values per
 // thread with 1024 threads (64 VGPRs of budget per lane for the panel); W
-// shrinks as the matrix grows so the panel stays in registers.
+// shrinks as the matrix grows so the panel stays in registers.  Single
+// precision up to 2048 rows: 16 columns as two register blocks of 8.
 template <typename T> inline int panel_width(int n) {
-    if (sizeof(T) == 4) return n <= 4096 ? 8 : 4;
+    if (sizeof(T) == 4) return n <= 2048 ? 16 : (n <= 4096 ? 8 : 4);
     return n <= 2048 ? 8 : (n <= 4096 ? 4 : 2);
 }
 
@@ -948,11 +1073,12 @@ template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
     return RPT * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
 }
 
-template <typename T, int NT, int RPT, int W>
+// H register blocks of W columns
+template <typename T, int NT, int RPT, int W, int H>
 harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
-    if constexpr (panel_fits_r<T, NT, RPT, W>()) {
-        HARP_PROF_EXT_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0, (getf2_kernel<T, NT, RPT, W>), dim3(batch), dim3(NT), 0,
-                             pa);
+    if constexpr (panel_fits_r<T, NT, RPT, W * H>()) {
+        HARP_PROF_EXT_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0, (getf2_kernel<T, NT, RPT, W, H>), dim3(batch), dim3(NT),
+                             0, pa);
         HARP_LAUNCH_CHECK();
         return HARP_OK;
     }
@@ -961,24 +1087,22 @@ harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
 
 // Two rows per thread while the panel is at most 2048 rows high (the
 // workgroup shrinks with the panel: fewer waves share the per-column
-// reductions), then more rows per thread with 1024 threads.
+// reductions), then more rows per thread with 1024 threads.  A 16-column
+// panel is two blocks of 8 and needs two rows per thread.
 template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
     if (pa.w > W) return HARP_E_ARG;
-    if constexpr (W >= 16) {   // 1024 threads would spill a 16-column panel
-        if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
-        if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
-        if (m <= 512 * 4) return launch_getf2_cfg<T, 512, 4, W>(pa, batch, st);
-        return HARP_E_ARG;
-    } else {
-        if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, W>(pa, batch, st);
-        if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, W>(pa, batch, st);
-        if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, W>(pa, batch, st);
-        if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, W>(pa, batch, st);
-        if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, W>(pa, batch, st);
-        return HARP_E_ARG;
+    constexpr int WB = W > 8 ? 8 : W, H = W / WB;
+    static_assert(WB * H == W && H <= 2, "panel width");
+    if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, WB, H>(pa, batch, st);
+    if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, WB, H>(pa, batch, st);
+    if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, WB, H>(pa, batch, st);
+    if constexpr (H == 1) {
+        if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, WB, H>(pa, batch, st);
+        if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, WB, H>(pa, batch, st);
     }
+    return HARP_E_ARG;
 }
 
 template <typename T>
