@@ -552,10 +552,10 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     }
     if constexpr (H == 2) {
         if (w2 > 0) {
-            // the second block, loaded once the first is factored (holding it
-            // through the first block's columns would cost 32 more registers)
-            // and its rows at the first block's top labels (the first
-            // block's exchanges are label swaps only)
+            // the second block, loaded once the first is factored (loading it
+            // with the first measured no faster and holds 32 more registers
+            // through the first block's columns), and its rows at the first
+            // block's top labels (the first block's exchanges are label swaps)
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int row = j0 + tid + r * NT;
