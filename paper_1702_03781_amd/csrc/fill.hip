@@ -25,9 +25,10 @@
 // instruction then writes 64 consecutive rows of one column (1 KB of
 // complex128): every store is a full, contiguous run.  Because the
 // coefficients C^{TS} now differ across the lanes of a wave (by T), the
-// coefficients of the current S for every T are staged in LDS as [p][q][T]
-// (a wave reads N_m consecutive complex values per (p, q): no bank
-// conflicts) and shared by the G source antennas of a lane.  The pair
+// coefficients of the current S for every T are staged in LDS as [p][T][q]
+// (a lane reads the Q + 1 coefficients of its (p, T) from one base address
+// with constant offsets; the N_m distinct runs of a wave fall in distinct
+// banks) and shared by the G source antennas of a lane.  The pair
 // geometry (t, w, phase, block kind) is computed once per pair into LDS.
 #include <math.h>
 
@@ -101,7 +102,8 @@ template <typename R, int Q, bool DUAL>
 __global__ void __launch_bounds__(256)
     fill_kernel(FillArgs a, const char* __restrict__ models, const double* __restrict__ px,
                 const double* __restrict__ py, void* __restrict__ Zout, float* __restrict__ Z32out) {
-    extern __shared__ __attribute__((aligned(16))) char fill_smem[];   // [np][Q+1][N_m] complex R
+    static_assert(Q >= 1, "Horner start");
+    extern __shared__ __attribute__((aligned(16))) char fill_smem[];   // [np][N_m][Q+1] complex R
     __shared__ PairGeo<R> geo;
     const int f = blockIdx.y;
     // antennas of this system (ns <= a.n_ant; the rest of the order is padding)
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(256)
 
     const R* coef = FillTraits<R>::coef(model, h);         // [T][S][p][q] complex
     const double* zself = reinterpret_cast<const double*>(model + h->off_self);
-    R* cf = reinterpret_cast<R*>(fill_smem);                // [p][q][T] complex
+    R* cf = reinterpret_cast<R*>(fill_smem);                // [p][T][q] complex
     const int npq = np * (Q + 1);
     using store_t = typename FillTraits<R>::store_t;
     store_t* Zf = reinterpret_cast<store_t*>(Zout) + size_t(f) * a.stride_z;
@@ -217,8 +219,10 @@ __global__ void __launch_bounds__(256)
         for (int e = tid; e < nm * npq; e += 256) {
             const int Tc = e / npq, pq = e % npq;
             const R* src = coef + 2 * (size_t(Tc * nm + S) * npq + pq);
-            cf[2 * (pq * nm + Tc)] = src[0];
-            cf[2 * (pq * nm + Tc) + 1] = src[1];
+            const int pp = pq / (Q + 1), q = pq % (Q + 1);
+            R* dst = cf + 2 * ((pp * nm + Tc) * (Q + 1) + q);
+            dst[0] = src[0];
+            dst[1] = src[1];
         }
         __syncthreads();
         // 4. two-level Horner for the lane's G source antennas
@@ -226,19 +230,21 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int g = 0; g < kG; ++g) acc[g] = cpx<R>{R(0), R(0)};
         if (wave_harp) {
+#pragma unroll 2
             for (int pp = np - 1; pp >= 0; --pp) {
                 R cr[Q + 1], ci[Q + 1];
 #pragma unroll
                 for (int q = 0; q <= Q; ++q) {
-                    const R* c = cf + 2 * ((pp * (Q + 1) + q) * nm + T);
+                    const R* c = cf + 2 * ((pp * nm + T) * (Q + 1) + q);
                     cr[q] = c[0];
                     ci[q] = c[1];
                 }
 #pragma unroll
                 for (int g = 0; g < kG; ++g) {
-                    R hr = cr[Q], hi = ci[Q];
+                    // the first step takes C_pQ as an operand (no copy into the accumulators)
+                    R hr = fma(cr[Q], t[g], cr[Q - 1]), hi = fma(ci[Q], t[g], ci[Q - 1]);
 #pragma unroll
-                    for (int q = Q - 1; q >= 0; --q) {
+                    for (int q = Q - 2; q >= 0; --q) {
                         hr = fma(hr, t[g], cr[q]);
                         hi = fma(hi, t[g], ci[q]);
                     }
