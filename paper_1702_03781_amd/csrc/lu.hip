@@ -730,7 +730,10 @@ struct LaswpArgs {
     int l_begin, l_end;    // ... and [l_begin, l_end) take the exchanges
 };
 
-template <typename T> struct LaswpCols { static constexpr int CB = 64 * 8 / int(2 * sizeof(T)); };
+// Columns per exchange workgroup: 64 bytes of each column row.  The scattered
+// 8- or 16-byte accesses are latency-bound, so many small workgroups (8 KB of
+// LDS each) beat few large ones: 64-column tiles took 2.6x as long per step.
+template <typename T> struct LaswpCols { static constexpr int CB = 8 * 8 / int(2 * sizeof(T)); };
 
 template <typename T>
 __global__ void __launch_bounds__(256) laswp_kernel(LaswpArgs la) {
@@ -940,13 +943,16 @@ __global__ void __launch_bounds__(256) group_perm_kernel(const int32_t* __restri
 
 // rows [g0, g0 + sb) of X after the group's row exchanges go to Tm (ld SB);
 // rows the exchanges push below the group are written back into X
+// right-hand sides per gather workgroup: many small workgroups (the gathered
+// rows are latency-bound scattered reads; 16 per workgroup took 2x as long)
+constexpr int kGatherCols = 2;
 template <typename T>
 __global__ void __launch_bounds__(256) group_gather_kernel(const int32_t* __restrict__ perm, int G, int g, int sb,
                                                            T* __restrict__ Xr, int64_t ldx, int64_t sX, int nrhs,
                                                            T* __restrict__ Tr, int64_t sT,
                                                            const int32_t* __restrict__ active) {
     using V = typename C2<T>::t;
-    constexpr int CG = 16;
+    constexpr int CG = kGatherCols;
     const int b = blockIdx.y;
     if (active && active[b] == 0) return;
     V* X = reinterpret_cast<V*>(Xr) + size_t(b) * sX;
@@ -1353,8 +1359,9 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     for (int gi = 0; gi < G; ++gi) {
         const int g0 = gi * kSB, sb = std::min(kSB, n - g0), gend = g0 + sb;
         HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
-                         hipLaunchKernelGGL((group_gather_kernel<T>), dim3((nrhs + 15) / 16, batch), dim3(256), 0,
-                                            st, perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
+                         hipLaunchKernelGGL((group_gather_kernel<T>),
+                                            dim3((nrhs + kGatherCols - 1) / kGatherCols, batch), dim3(256), 0, st,
+                                            perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
         HARP_LAUNCH_CHECK();
         const T* Linv = aux + 2 * (int64_t(gi) * kRec);
         if ((s = gemm(sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX, T(1), T(0))) !=
