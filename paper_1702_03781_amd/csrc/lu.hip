@@ -995,16 +995,19 @@ __global__ void __launch_bounds__(256) convert_kernel(const Ti* __restrict__ src
                                                       int cols, const int32_t* active) {
     const int b = blockIdx.z;
     if (active && active[b] == 0) return;
-    const int64_t total = int64_t(rows) * cols;
     src += size_t(b) * ss;
     dst += size_t(b) * sd;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t c = e / rows, r = e % rows;
-        const Ti v = src[c * lds + r];
+    // work units of 256 rows of one column (the unit index is uniform, so
+    // there is no per-element division)
+    const int chunks = (rows + 255) / 256, units = chunks * cols;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
+        if (r >= rows) continue;
+        const Ti v = src[int64_t(c) * lds + r];
         To o;
         o.x = decltype(o.x)(v.x);
         o.y = decltype(o.y)(v.y);
-        dst[c * ldd + r] = o;
+        dst[int64_t(c) * ldd + r] = o;
     }
 }
 
@@ -1015,16 +1018,17 @@ __global__ void __launch_bounds__(256) axpy_kernel(double2* __restrict__ X, int6
                                                    int cols, const int32_t* active) {
     const int b = blockIdx.z;
     if (active && active[b] == 0) return;
-    const int64_t total = int64_t(rows) * cols;
     X += size_t(b) * sx;
     D += size_t(b) * sd;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t c = e / rows, r = e % rows;
-        const Vd d = D[c * ldd + r];
-        double2 x = X[c * ldx + r];
+    const int chunks = (rows + 255) / 256, units = chunks * cols;   // as in convert_kernel
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
+        if (r >= rows) continue;
+        const Vd d = D[int64_t(c) * ldd + r];
+        double2 x = X[int64_t(c) * ldx + r];
         x.x += double(d.x);
         x.y += double(d.y);
-        X[c * ldx + r] = x;
+        X[int64_t(c) * ldx + r] = x;
     }
 }
 
@@ -1034,11 +1038,12 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __res
                                                             int rows, int cols, double* __restrict__ part) {
     const int b = blockIdx.z;
     M += size_t(b) * s;
-    const int64_t total = int64_t(rows) * cols;
     double acc = 0.0;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t c = e / rows, r = e % rows;
-        const double2 v = M[c * ld + r];
+    const int chunks = (rows + 255) / 256, units = chunks * cols;   // as in convert_kernel
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
+        if (r >= rows) continue;
+        const double2 v = M[int64_t(c) * ld + r];
         acc = fma(v.x, v.x, fma(v.y, v.y, acc));
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
