@@ -824,7 +824,7 @@ __global__ void __launch_bounds__(256) rank_update_kernel(RankArgs ra) {
 template <typename T>
 harp_status launch_rank_update(void* A, int64_t lda, int64_t sA, int n, int j0, int w, int c_end, int batch,
                                hipStream_t st) {
-    constexpr int CN = 8;
+    constexpr int CN = 4;
     const int M = n - j0 - w, N = c_end - j0 - w;
     if (w < 1 || w > 16 || M <= 0 || N <= 0) return HARP_E_ARG;
     const dim3 grid(unsigned((M + 255) / 256), unsigned((N + CN - 1) / CN), unsigned(batch));
