@@ -689,24 +689,22 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
         if (t < w2) Ls[W + t][c] = stage[nother + c][t];
     }
     __syncthreads();
-    // unit-lower solve of the top rows of the right columns
-    // (one column per thread: the outer block is narrower than the workgroup,
-    // and a single pass keeps the LDS reads of Ls out of any loop)
-    static_assert(NBMAX <= NT, "one thread per column of the outer block");
-    if (const int oc = left + tid; oc < nother) {
+    // unit-lower solve of the top rows of the right columns: one 16-lane
+    // group per column and one lane per row, so the substitution is WT steps
+    // of one broadcast (a lane shuffle within the group) and one multiply-add,
+    // instead of a chain of WT (WT - 1) / 2 multiply-adds in one lane
+    static_assert(WT <= 16, "one lane per top row");
+    for (int oc = left + (tid >> 4); oc < nother; oc += NT / 16) {
+        const int i = tid & 15;
         const int col = j0 + w + (oc - left);
-        V x[WT];
+        const int ic = i < WT ? i : WT - 1;   // rows past the panel: never used
+        V x = i < w ? stage[oc][i] : V{T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i < WT; ++i) x[i] = i < w ? stage[oc][i] : V{T(0), T(0)};
-        // column-oriented substitution: x[q] is final once reached (the
-        // compiler fence keeps the reads of L to one column at a time)
-#pragma unroll
-        for (int q = 0; q < WT; ++q) {
-            if (q < w) A[size_t(col) * lda + j0 + q] = x[q];
-#pragma unroll
-            for (int i = q + 1; i < WT; ++i) x[i] = cfms(x[i], Ls[i][q], x[q]);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        for (int q = 0; q < WT - 1; ++q) {
+            const V xq = V{__shfl(x.x, q, 16), __shfl(x.y, q, 16)};
+            if (i > q && i < w) x = cfms(x, Ls[ic][q], xq);
         }
+        if (i < w) A[size_t(col) * lda + j0 + i] = x;
     }
     if (pa.blk) {
         __shared__ BlkShared<T> bs;
