@@ -294,8 +294,8 @@ inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, do
 // the LU's thin catch-up, deferred-row and in-block products) take 32 x 32
 // tiles for four times the workgroups.  A product in place (D = B) keeps
 // 64-row tiles so that one workgroup reads a whole column block of B before
-// writing it (callers use it with M <= 64); narrow ones (N <= 32) the 64 x 32
-// tile.
+// writing it (callers use it with M <= 64), 32 columns wide for twice the
+// workgroups; narrow ones (N <= 32) take the same 64 x 32 tile.
 template <typename T>
 inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
     if (g.M <= 0 || g.N <= 0 || batch <= 0 || g.inner <= 0) return HARP_OK;
@@ -315,7 +315,7 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
         // long FP64 contractions (the refinement residual): 8-wide K chunks at
         // two workgroups per CU measured ~1.5 % faster than 16-wide at one
         launch_cgemm<T, 64, 64, 8, 4, 1, 2>(g, batch, stream, flops, bytes);
-    else if (g.N <= 32)
+    else if (g.N <= 32 || in_place)
         launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
     else
         launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream, flops, bytes);
