@@ -425,12 +425,12 @@ __device__ inline void linv_level(BlkShared<T>& bs, int tid) {
 // Last panel of an outer block [k0, kend): with the block's unit-lower
 // diagonal block now final in A, write its inverse and the block's row
 // exchange map to the block scratch.  The inverse is blocked: 16 x 16
-// diagonal blocks by substitution (one thread per column), then two doubling
-// levels of products.
+// diagonal blocks by substitution (a lane per entry), then two doubling levels
+// of products.
 template <typename T, int NT>
 __device__ void block_finish(const PanelArgs& pa, int b, int tid, BlkShared<T>& bs) {
     using V = typename C2<T>::t;
-    static_assert(NT >= 64, "one thread per column of the 16 x 16 diagonal blocks");
+    static_assert(NT >= 64 && 1024 % NT == 0, "whole 16-lane groups in every pass");
     __syncthreads();   // this workgroup's writes of the panel and its exchanges are visible
     const V* A = reinterpret_cast<const V*>(pa.A) + size_t(b) * pa.sA;
     const int k0 = pa.k0, nbo = pa.kend - pa.k0, n = pa.n;
@@ -455,25 +455,18 @@ __device__ void block_finish(const PanelArgs& pa, int b, int tid, BlkShared<T>& 
         map[tid] = r;
         map[2 * NBMAX + tid] = src;
     }
-    // 16 x 16 diagonal blocks: thread (d, c) forms column c of block d's inverse
-    if (tid < 64) {
-        const int o = 16 * (tid >> 4), c = tid & 15;
-        V x[16];
+    // 16 x 16 diagonal blocks: column c of block d's inverse by forward
+    // substitution with a lane per row i (16-lane groups), x_q taken by a lane
+    // shuffle once final; stored transposed in the upper part
+    for (int e = tid; e < 4 * 16 * 16; e += NT) {
+        const int o = 16 * (e >> 8), c = (e >> 4) & 15, i = e & 15;
+        V x = V{i == c ? T(1) : T(0), T(0)};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (i <= c) {
-                x[i] = V{i == c ? T(1) : T(0), T(0)};
-                continue;
-            }
-            V acc = bs.M[o + i][o + c];
-#pragma unroll
-            for (int k = 0; k < i; ++k)
-                if (k > c) acc = cfma(acc, bs.M[o + i][o + k], x[k]);
-            x[i] = V{-acc.x, -acc.y};
+        for (int q = 0; q < 15; ++q) {
+            const V xq = V{__shfl(x.x, q, 16), __shfl(x.y, q, 16)};
+            if (i > q && q >= c) x = cfms(x, bs.M[o + i][o + q], xq);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i > c) bs.M[o + c][o + i] = x[i];
+        if (i > c) bs.M[o + c][o + i] = x;
     }
     __syncthreads();
     linv_level<T, NT, 16>(bs, tid);
