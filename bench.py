@@ -33,6 +33,7 @@ PEAK = {  # MI355X published dense peaks
     "fp32_mfma_tflops": 157.3,
     "fp64_mfma_tflops": 78.6,
     "fp64_vector_tflops": 78.6,
+    "fp32_vector_tflops": 157.3,
 }
 REL_GATE = 1e-6
 
@@ -55,44 +56,7 @@ KERNEL_SOURCES = {
 }
 
 
-def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
-    """The FP64 oracle (fill, LAPACK solve, admittances) on a sample of the
-    workload's frequencies, on this host's cores."""
-    import numpy as np
-
-    from oracle import fill as ofill, fit as ofit, solve as osolve
-    models = [ofit.fit(wl.freqs[i], wl.elem.samples, wl.P[i], wl.Q, wl.r_min,
-                       wire_radius=wl.elem.wire_radius) for i in freq_idx]
-    t0 = time.perf_counter()
-    passes = 0
-    while True:                      # whole passes over the sample, ~10 s of CPU work
-        for m in models:
-            Z = ofill.fill(m, wl.x, wl.y)
-            X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
-            Y = osolve.admittance(X, m.w, wl.n_ant)
-            assert np.isfinite(Y).all()
-        passes += 1
-        if time.perf_counter() - t0 >= min_seconds or passes >= max_passes:
-            break
-    dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    # the same work for one frequency on one thread
-    one_thread = None
-    try:
-        from threadpoolctl import threadpool_limits
-        m = models[0]
-        with threadpool_limits(limits=1):
-            t1 = time.perf_counter()
-            Z = ofill.fill(m, wl.x, wl.y)
-            X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
-            osolve.admittance(X, m.w, wl.n_ant)
-            one_thread = wl.n_ant / (time.perf_counter() - t1)
-    except Exception:  # pragma: no cover
-        one_thread = None
+def _host():
     cpu_model = None
     try:
         with open("/proc/cpuinfo") as fh:
@@ -102,19 +66,105 @@ def cpu_baseline(wl, freq_idx, min_seconds=10.0, max_passes=8):
                     break
     except OSError:  # pragma: no cover
         pass
+    return {"cpu_model": cpu_model, "nproc": os.cpu_count()}
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _port_rel(a, b):
+    import numpy as np
+    return float((np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max())
+
+
+def cpu_baseline(wl, freq_idx, X_gpu=None, Y_gpu=None, min_seconds=10.0, max_passes=4):
+    """The FP64 oracle (its own model fit, Eq. 4 fill, LAPACK solve with one
+    right-hand side per port, admittances) over whole passes of a sample of
+    the workload's frequencies on this host's cores, and the GPU results of
+    the same frequencies against it (X_gpu, Y_gpu: [n_freq] host arrays)."""
+    import numpy as np
+
+    from oracle import fill as ofill, fit as ofit, solve as osolve
+    models = [ofit.fit(wl.freqs[i], wl.elem.samples, wl.P[i], wl.Q, wl.r_min,
+                       wire_radius=wl.elem.wire_radius) for i in freq_idx]
+    t0 = time.perf_counter()
+    passes = 0
+    last = {}
+    while True:                      # whole passes over the sample, ~10 s of CPU work
+        for i, m in zip(freq_idx, models):
+            Z = ofill.fill(m, wl.x, wl.y, wl.ri)
+            X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
+            Y = osolve.admittance(X, m.w, wl.n_ant)
+            last[i] = (X, Y)
+        passes += 1
+        if time.perf_counter() - t0 >= min_seconds or passes >= max_passes:
+            break
+    dt = time.perf_counter() - t0
+    # the same work for one frequency on one thread
+    one_thread = None
+    try:
+        from threadpoolctl import threadpool_limits
+        m = models[0]
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            Z = ofill.fill(m, wl.x, wl.y, wl.ri)
+            X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
+            osolve.admittance(X, m.w, wl.n_ant)
+            one_thread = wl.n_ant / (time.perf_counter() - t1)
+    except Exception:  # pragma: no cover
+        one_thread = None
+    acc = None
+    if X_gpu is not None:
+        ex = {float(wl.freqs[i]): _port_rel(X_gpu[i], last[i][0]) for i in freq_idx}
+        ey = {float(wl.freqs[i]): _rel(Y_gpu[i], last[i][1]) for i in freq_idx}
+        acc = {"max_rel_err_X_per_port": max(ex.values()), "max_rel_err_Y": max(ey.values()),
+               "per_freq_X": {f"{k / 1e6:.0f} MHz": v for k, v in ex.items()},
+               "per_freq_Y": {f"{k / 1e6:.0f} MHz": v for k, v in ey.items()},
+               "gate": REL_GATE,
+               "ok": max(ex.values()) <= REL_GATE and max(ey.values()) <= REL_GATE,
+               "note": "GPU path (GPU model build, fill, complex64 LU, FP64 refinement) against the "
+                       "oracle (its own FP64 model fit, Eq. 4 fill, LAPACK) on the same seeded inputs"}
     return {
         "value": passes * len(freq_idx) * wl.n_ant / dt,
         "unit": "port solves/s",
-        "cores": int(cores),
+        "cores": int(_blas_threads()),
         "kind": "oracle",
-        "sample": (f"{passes} pass(es) over {len(freq_idx)} of the 16 frequencies "
+        "sample": (f"{passes} pass(es) over {len(freq_idx)} of the {len(wl.freqs)} frequencies "
                    f"({', '.join(f'{wl.freqs[i] / 1e6:.0f}' for i in freq_idx)} MHz): "
                    f"oracle Eq. 4 fill + LAPACK zgesv with {wl.n_ant} RHS + admittances, "
                    f"{dt:.1f} s wall"),
         "seconds": dt,
         "one_thread_port_solves_per_s": one_thread,
-        "host": {"cpu_model": cpu_model, "nproc": os.cpu_count()},
-    }
+        "host": _host(),
+    }, acc
+
+
+def cpu_small16():
+    """The oracle on the 16-element case (n = 64, 16 ports), repeated ~1 s."""
+    from oracle import fill as ofill, fit as ofit, solve as osolve
+    from workloads import workload
+    wl = workload("small16")
+    m = ofit.fit(wl.freqs[0], wl.elem.samples, wl.P[0], wl.Q, wl.r_min, wire_radius=wl.elem.wire_radius)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 1.0:
+        Z = ofill.fill(m, wl.x, wl.y)
+        X = osolve.solve(Z, osolve.port_rhs(m.w, wl.n_ant))
+        osolve.admittance(X, m.w, wl.n_ant)
+        reps += 1
+    dt = time.perf_counter() - t0
+    return {"value": reps * wl.n_ant / dt, "unit": "port solves/s", "cores": int(_blas_threads()),
+            "kind": "oracle", "sample": f"{reps} repetitions of the 16-element case (n = 64, 16 ports)"}
 
 
 def class_rates(prof, steps):
@@ -132,21 +182,54 @@ def class_rates(prof, steps):
     return out
 
 
-def roofline_from_prof(prof, steps):
+def method_flops(n, nrhs, iters, refined=True):
+    """Algorithmic flops of one pass of the solver over len(iters) systems of
+    order n with nrhs right-hand sides: LU 8n^3/3 each; triangular solves
+    8 n^2 nrhs per solve (one initial solve plus one per correction); the FP64
+    residuals 8 n^2 nrhs each (one per check: one more than corrections)."""
+    lu = len(iters) * 8.0 * n ** 3 / 3.0
+    if not refined:
+        return {"lu": lu, "solves": len(iters) * 8.0 * n * n * nrhs, "residuals": 0.0}
+    solves = sum(1 + it for it in iters) * 8.0 * n * n * nrhs
+    resid = sum(1 + it for it in iters) * 8.0 * n * n * nrhs
+    return {"lu": lu, "solves": solves, "residuals": resid}
+
+
+def attribute_method_flops(prof, steps, work, fill_flops_step, refined=True):
+    """Method flops per kernel class over the timed steps: the FP32 (or FP64)
+    matrix-core class takes the LU and solve flops that the panel and rank-w
+    update kernels do not do themselves; the FP64 class of the refined path
+    the residuals; the fill its Eq. 4 flops."""
+    lu_cls = "gemm_c64" if refined else "gemm_c128"
+    other = prof["getf2"]["flops"] + prof["rank_update"]["flops"]
+    out = {lu_cls: (work["lu"] + work["solves"]) * steps - other,
+           "getf2": prof["getf2"]["flops"], "rank_update": prof["rank_update"]["flops"],
+           "fill": fill_flops_step * steps}
+    if refined:
+        out["gemm_c128"] = work["residuals"] * steps
+    return out
+
+
+def roofline_from_prof(prof, steps, mflops):
     """Roofline of the kernel class with the largest summed time, from the
-    library's dispatch-attached kernel timers."""
+    library's dispatch-attached kernel timers, charged with the method's own
+    flops (mflops: per class over the timed steps)."""
     cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
                                                     "trsm_lower", "trsm_upper", "rank_update")}
     dom = max(cand, key=lambda k: cand[k]["ms"])
     pd = prof[dom]
-    avg_ms = pd["ms"] / max(1, pd["launches"])
+    launches = max(1, pd["launches"])
+    avg_ms = pd["ms"] / launches
     if dom == "fill":
         bound, peak, unit = "alu", PEAK["fp64_vector_tflops"], "TFLOP/s"
-        achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
+        achieved = mflops["fill"] / (pd["ms"] * 1e-3) / 1e12
     elif dom in ("gemm_c64", "gemm_c128"):
         bound = "mfma"
         peak = PEAK["fp32_mfma_tflops"] if dom == "gemm_c64" else PEAK["fp64_mfma_tflops"]
         unit = "TFLOP/s"
+        achieved = mflops[dom] / (pd["ms"] * 1e-3) / 1e12
+    elif dom == "getf2":
+        bound, peak, unit = "alu", PEAK["fp32_vector_tflops"], "TFLOP/s"
         achieved = pd["flops"] / (pd["ms"] * 1e-3) / 1e12
     elif dom == "rank_update":
         bound, peak, unit = "hbm", PEAK["hbm_gbs"], "GB/s"
@@ -172,14 +255,37 @@ def roofline_from_prof(prof, steps):
         "traffic": traffic,
         "launches_per_step": pd["launches"] / steps,
         "avg_launch_ms": avg_ms,
-        "algorithmic_flops_per_launch": pd["flops"] / max(1, pd["launches"]),
-        "algorithmic_bytes_per_launch": pd["bytes"] / max(1, pd["launches"]),
+        "algorithmic_flops_per_launch": mflops.get(dom, pd["flops"]) / launches,
+        "algorithmic_bytes_per_launch": pd["bytes"] / launches,
+        "flops_charged": "method flops: LU 8n^3/3 and triangular solves 8n^2 N_rhs per solve (measured "
+                         "sweep count), less the panel and rank-w kernels' own; FP64 residual 8n^2 N_rhs "
+                         "per check; fill 2(2P+1)(2Q+4) per model-evaluated entry",
     }
+
+
+def step_roofs(work, fill_flops, refined=True):
+    """Time of one step if every part ran at its roof: FP32 matrix cores for
+    the complex64 LU and solves (FP64 for the plain path), FP64 matrix cores
+    for the residuals, FP64 vector units for the fill."""
+    lu_peak = PEAK["fp32_mfma_tflops"] if refined else PEAK["fp64_mfma_tflops"]
+    t_lu = (work["lu"] + work["solves"]) / (lu_peak * 1e12)
+    t_res = work["residuals"] / (PEAK["fp64_mfma_tflops"] * 1e12)
+    t_fill = fill_flops / (PEAK["fp64_vector_tflops"] * 1e12)
+    return {"ms": 1e3 * (t_lu + t_res + t_fill), "lu_and_solves_ms": 1e3 * t_lu,
+            "residuals_ms": 1e3 * t_res, "fill_ms": 1e3 * t_fill}
+
+
+def fill_flops_of(P_list, Q, n_ant_pairs, n_mbf):
+    """2(2P+1)(2Q+4) flops per model-evaluated entry, summed over models."""
+    return sum(2.0 * (2 * P + 1) * (2 * Q + 4) for P in P_list) * n_ant_pairs * n_mbf ** 2
 
 
 def bench_batched(args, api, torch, dev):
     """48 station layouts of 64-512 elements, each at 8 of the 16 sweep
-    frequencies (384 systems, n = 528-4056), reusing the 16 models."""
+    frequencies (384 systems, n = 528-4056), reusing the 16 models; one step
+    is one replay of the HIP graph that holds every group's fill, excitation,
+    factorisation, refined solve and admittances (--no-graph: eager, the
+    refinement reporting to the host once per group)."""
     import numpy as np
 
     from workloads import batched_layouts, workload
@@ -192,13 +298,9 @@ def bench_batched(args, api, torch, dev):
     layouts = batched_layouts()
     # the planner's cost model measured on this GPU (one group per point)
     cost, cost_points = api.autotune_batch_costs(mb)
-    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost)
-    S.step()
+    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost, graph=not args.no_graph)
+    S.step()                              # raises on a domain error or a zero pivot
     torch.cuda.synchronize()
-    infos = [int(S.system(s)[2]) for s in range(S.n_systems)] + [int(S.system(s)[3])
-                                                                 for s in range(S.n_systems)]
-    if any(infos):
-        raise RuntimeError("fill domain error or zero pivot")
     conv = all(r["converged"] for r in S.reports)
     # accuracy gate on the smallest, a middle and the largest system: the
     # refined batch against the plain complex128 GPU path of that layout alone
@@ -227,23 +329,38 @@ def bench_batched(args, api, torch, dev):
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     iters = sorted({r["iters"] for r in S.reports})
 
+    # kernel-class timers need eager launches: a timed pass of the eager path
+    E = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost) if not args.no_graph else S
+    E.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3
     api.prof_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        S.step()
+    E.step()
     torch.cuda.synchronize()
-    ms_instr = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_instr = (time.perf_counter() - t0) * 1e3
     prof = api.prof_read()
     api.prof_enable(False)
+    e_iters = [E.reports[s]["iters"] for s in range(E.n_systems)]
+    del E
     fill_flops_step = 0.0
+    lu = solves = resid = 0.0
+    for g in S.groups:
+        w = method_flops(g.n, g.n_ports_pad, [e_iters[m] for m in g.members])
+        lu, solves, resid = lu + w["lu"], solves + w["solves"], resid + w["residuals"]
     for s in range(S.n_systems):
         li, f = S.layout_of[s]
         na_s = S.n_ant[s]
-        fill_flops_step += 2.0 * (2 * wl.P[f] + 1) * (2 * wl.Q + 4) * na_s * (na_s - 1) * wl.elem.n_mbf ** 2
-    prof["fill"]["flops"] = fill_flops_step * args.steps
+        fill_flops_step += fill_flops_of([wl.P[f]], wl.Q, na_s * (na_s - 1), wl.elem.n_mbf)
+    work = {"lu": lu, "solves": solves, "residuals": resid}
+    mfl = attribute_method_flops(prof, 1, work, fill_flops_step, refined=True)
     for v in prof.values():
-        v["ms_per_step"] = v["ms"] / args.steps
-    roofline = roofline_from_prof(prof, args.steps)
+        v["ms_per_step"] = v["ms"]
+    roofline = roofline_from_prof(prof, 1, mfl)
+    roof = step_roofs(work, fill_flops_step)
 
     nm = wl.elem.n_mbf
     port_solves = float(sum(S.n_ant))
@@ -257,6 +374,7 @@ def bench_batched(args, api, torch, dev):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_eager": ms_eager,
         "ms_per_step_with_kernel_timers": ms_instr,
         "higher_is_better": True,
         "scaling": "weak",
@@ -269,20 +387,48 @@ def bench_batched(args, api, torch, dev):
                          "16 frequencies 50-350 MHz each (384 systems, n = 528-4056, N_a ports each); "
                          "grouped and padded, complex64 LU on MFMA + FP64 refinement"),
             "systems": S.n_systems, "groups": [(len(g.members), g.n) for g in S.groups],
-            "streams": args.streams, "refine_tol": args.tol,
+            "streams": args.streams, "refine_tol": args.tol, "graph": not args.no_graph,
+            "graph_sweep_budget": S.sweeps if not args.no_graph else None,
             "padded_over_real_entries": padded / entries,
             "plan_cost_model": {"t_group_s": cost[0], "t_order_s": cost[1], "t_system_s": cost[2],
                                 "measured": cost_points},
         },
-        "reduced_z_entries_per_s": entries / (ms * 1e-3),
+        "reduced_z_entries_per_s_whole_step": entries / (ms * 1e-3),
         "accuracy": {"max_rel_err_X_vs_plain": rel_x, "max_rel_err_Y_vs_plain": rel_y,
                      "all_converged": conv, "gate": REL_GATE, "ok": accuracy_ok,
                      "refine_iters": iters, "checked_systems": picks},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
-        "kernel_classes": class_rates(prof, args.steps),
+        "kernel_classes": class_rates(prof, 1),
         "roofline": roofline,
+        "step_roofline": {**{k: round(v, 3) for k, v in roof.items()}, "measured_ms": ms, "frac": roof["ms"] / ms},
         "cpu_baseline": None,
     }
+    if args.cpu_freqs > 0:
+        # the oracle on the three checked systems (each its own model fit,
+        # fill, LAPACK solve and admittances), and the GPU batch against it
+        from oracle import fill as ofill, fit as ofit, solve as osolve
+        t_cpu, ports, ex, ey = 0.0, 0, 0.0, 0.0
+        for s in picks:
+            li, f = S.layout_of[s]
+            x, y, _ = layouts[li]
+            m = ofit.fit(wl.freqs[f], wl.elem.samples, wl.P[f], wl.Q, wl.r_min, wire_radius=wl.elem.wire_radius)
+            t0 = time.perf_counter()
+            Zo = ofill.fill(m, x, y)
+            Xo = osolve.solve(Zo, osolve.port_rhs(m.w, x.size))
+            Yo = osolve.admittance(Xo, m.w, x.size)
+            t_cpu += time.perf_counter() - t0
+            ports += x.size
+            X, Y, _, _ = S.system(s)
+            ex = max(ex, _port_rel(X.cpu().numpy(), Xo))
+            ey = max(ey, _rel(Y.cpu().numpy(), Yo))
+        out["cpu_baseline"] = {"value": ports / t_cpu, "unit": "port solves/s", "cores": int(_blas_threads()),
+                               "kind": "oracle",
+                               "sample": f"the smallest, a middle and the largest system ({ports} ports): oracle "
+                                         f"Eq. 4 fill + LAPACK zgesv + admittances, {t_cpu:.1f} s",
+                               "host": _host()}
+        out["accuracy"]["vs_oracle"] = {"max_rel_err_X_per_port": ex, "max_rel_err_Y": ey,
+                                        "ok": ex <= REL_GATE and ey <= REL_GATE}
+        out["accuracy"]["ok"] = accuracy_ok and ex <= REL_GATE and ey <= REL_GATE
     print(json.dumps(out), flush=True)
 
 
@@ -358,9 +504,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-10, help="FP64 refinement tolerance")
-    ap.add_argument("--cpu-freqs", type=int, default=8,
-                    help="frequencies in the CPU-baseline sample (0: skip)")
+    ap.add_argument("--cpu-freqs", type=int, default=16,
+                    help="frequencies of the station sweep in the CPU-baseline sample (0: skip every CPU leg)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-array (n = 8192) steps")
     ap.add_argument("--workload", choices=["station", "batched", "tessellated"], default="station",
                     help="station: the 16-frequency station sweep (default); batched: 48 unequal "
                          "layouts x 8 frequencies; tessellated: the 1024-element array by overlapping "
@@ -368,6 +515,7 @@ def main():
     ap.add_argument("--r-in", type=float, default=6.0, help="tessellation inner radius (m)")
     ap.add_argument("--r-ext", type=float, default=6.0, help="tessellation extension (m)")
     ap.add_argument("--streams", type=int, default=4, help="HIP streams of the batched and tessellated workloads")
+    ap.add_argument("--no-graph", action="store_true", help="batched workload: eager launches instead of a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (the reference kernel that "
                          "scales the HBM byte counters) and exit")
@@ -418,16 +566,17 @@ def main():
     ref = api.StationSolver(mb, x, y, "refined", tol=args.tol)
     plain = api.StationSolver(mb, x, y, "plain")
 
-    # accuracy gate: refined path vs the plain FP64 GPU path
+    # accuracy gate: refined path vs the plain FP64 GPU path (the oracle
+    # comparison follows in the CPU leg); step() raises on a fill domain error
+    # or a zero pivot
     Xr, Yr = ref.step()
     Xp, Yp = plain.step()
     torch.cuda.synchronize()
-    if int(ref.info.max()) != 0 or int(ref.finfo.max()) != 0 or int(plain.finfo.max()) != 0:
-        raise RuntimeError("fill domain error or zero pivot")
     d = (Xr - Xp).abs().pow(2).sum(dim=(1, 2)).sqrt() / Xp.abs().pow(2).sum(dim=(1, 2)).sqrt()
     dy = (Yr - Yp).abs().pow(2).sum(dim=(1, 2)).sqrt() / Yp.abs().pow(2).sum(dim=(1, 2)).sqrt()
     rel_x, rel_y = float(d.max()), float(dy.max())
     accuracy_ok = rel_x <= REL_GATE and rel_y <= REL_GATE
+    X_host, Y_host = Xr.cpu().numpy(), Yr.cpu().numpy()
 
     def timed(solver, steps):
         for _ in range(args.warmup):
@@ -479,15 +628,19 @@ def main():
     api.prof_enable(False)
 
     ms_plain = None if args.no_plain else timed(plain, max(3, args.steps // 4))
+    del plain, Xp, Yp
 
-    # algorithmic work of the fill: (2P+1)(2Q+4) real FMA per model-evaluated entry
-    fill_flops_step = sum(2.0 * (2 * P + 1) * (2 * wl.Q + 4) for P in wl.P) * \
-        (na * (na - 1)) * wl.elem.n_mbf ** 2
-    prof["fill"]["flops"] = fill_flops_step * args.steps
+    # algorithmic work per step and the method flops of each kernel class
+    fill_flops_step = fill_flops_of(wl.P, wl.Q, na * (na - 1), wl.elem.n_mbf)
+    work = method_flops(n, na, iters, refined=True)
+    mfl = attribute_method_flops(prof, args.steps, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
-
-    roofline = roofline_from_prof(prof, args.steps)
+    roofline = roofline_from_prof(prof, args.steps, mfl)
+    roof_ref = step_roofs(work, fill_flops_step, refined=True)
+    work_plain = method_flops(n, na, [0] * nf, refined=False)
+    roof_plain = step_roofs(work_plain, fill_flops_step, refined=False)
+    t_fill = prof["fill"]["ms_per_step"] * 1e-3
 
     port_solves = nf * na
     value = port_solves / (ms * 1e-3)
@@ -515,14 +668,22 @@ def main():
             "n_ant": na, "n_mbf": wl.elem.n_mbf, "n_freq": nf, "n": n, "rhs_per_freq": na,
             "P": list(wl.P), "Q": wl.Q, "refine_tol": args.tol,
         },
-        "reduced_z_entries_per_s": nf * n * n / (ms * 1e-3),
-        "fill_entries_per_s": nf * n * n / (prof["fill"]["ms_per_step"] * 1e-3)
-        if prof["fill"]["ms"] > 0 else None,
+        # entries/s over the fill's own time (the fill kernel's timers); the
+        # port solves over the factorisation and solve phases
+        "reduced_z_entries_per_s": nf * n * n / t_fill if t_fill > 0 else None,
+        "reduced_z_entries_per_s_whole_step": nf * n * n / (ms * 1e-3),
+        "port_solves_per_s_factor_and_solve": port_solves / ((phase_ms["factor"] + phase_ms["solve_and_refine"])
+                                                              * 1e-3),
         "accuracy": {"max_rel_err_X_vs_plain": rel_x, "max_rel_err_Y_vs_plain": rel_y,
                      "gate": REL_GATE, "ok": accuracy_ok, "refine_iters": iters},
         "plain_fp64": None if ms_plain is None else {
             "ms_per_step": ms_plain, "port_solves_per_s": port_solves / (ms_plain * 1e-3),
-            "speedup_refined_over_plain": ms_plain / ms},
+            "speedup_refined_over_plain": ms_plain / ms,
+            "step_at_roofs_ms": roof_plain["ms"], "step_roof_frac": roof_plain["ms"] / ms_plain},
+        "step_roofline": {**{k: round(v, 4) for k, v in roof_ref.items()}, "measured_ms": ms,
+                          "frac": roof_ref["ms"] / ms,
+                          "parts": "FP32 matrix cores: LU + solves; FP64 matrix cores: residuals; FP64 vector: "
+                                   "fill"},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
         "kernel_classes": class_rates(prof, args.steps),
         "roofline": roofline,
@@ -532,10 +693,50 @@ def main():
                                       "frequency (Table II); not this workload"},
         "cpu_baseline": None,
     }
+    del ref, Xr, Yr
+    torch.cuda.empty_cache()
+
+    # the large array (1024 elements, 38 m, 200 MHz, radius of influence 12 m,
+    # n = 8192, 1024 ports): a few refined steps on the same launch path
+    large = None
+    if not args.no_large:
+        wl5 = workload("large1024")
+        model5 = api.harp_fit(samples, wl5.elem.wire_radius, wl5.freqs[0], wl5.P[0], wl5.Q, wl5.r_min)
+        mb5 = api.stack_models([model5])
+        S5 = api.StationSolver(mb5, torch.from_numpy(wl5.x).to(dev), torch.from_numpy(wl5.y).to(dev), "refined",
+                               tol=args.tol, ri=wl5.ri)
+        ms5 = timed(S5, 3)
+        ev5 = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        S5.step(events=ev5)
+        torch.cuda.synchronize()
+        ph5 = {k: ev5[i].elapsed_time(ev5[i + 1]) for i, k in enumerate(phase_names)}
+        it5 = [r["iters"] for r in S5.reports]
+        n5 = wl5.n
+        large = {"workload": "large array: 1024 elements (38 m disk), 8 MBFs x 64 samples, 200 MHz, radius of "
+                             "influence 12 m, n = 8192, 1024 ports; complex64 LU + FP64 refinement",
+                 "steps": 3, "ms_per_step": ms5, "port_solves_per_s": wl5.n_ant / (ms5 * 1e-3),
+                 "reduced_z_entries_per_s": n5 * n5 / (ph5["fill_and_excitation"] * 1e-3),
+                 "phase_ms": {k: round(v, 3) for k, v in ph5.items()}, "refine_iters": it5,
+                 "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5), 0.0)["ms"]}
+        X5, Y5 = S5.X[0].cpu().numpy(), S5.Y[0].cpu().numpy()
+        del S5
+        torch.cuda.empty_cache()
+    out["large_array"] = large
+
     if args.cpu_freqs > 0:
         k = min(args.cpu_freqs, nf)
         idx = sorted(set(int(round(i)) for i in np.linspace(0, nf - 1, k)))
-        out["cpu_baseline"] = cpu_baseline(wl, idx)
+        out["cpu_baseline"], acc = cpu_baseline(wl, idx, X_host, Y_host)
+        out["accuracy"]["vs_oracle"] = acc
+        out["accuracy"]["ok"] = accuracy_ok and acc["ok"]
+        out["cpu_baseline_small16"] = cpu_small16()
+        if large is not None:
+            wl5 = workload("large1024")
+            cb5, acc5 = cpu_baseline(wl5, [0], X5[None], Y5[None], min_seconds=0.0, max_passes=1)
+            cb5["sample"] = "one pass of the large array (n = 8192, 1024 ports; fill within RI 12 m): " + \
+                            cb5["sample"].split(": ", 1)[1]
+            large["cpu_baseline"] = cb5
+            large["accuracy_vs_oracle"] = acc5
     print(json.dumps(out), flush=True)
 
 

@@ -271,13 +271,16 @@ harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void *d_A
                            int64_t stride_a, int32_t *d_ipiv, int32_t *d_info, void *d_aux,
                            size_t aux_bytes, hipStream_t stream);
 
-/* FP64 iterative refinement of a solve whose factors are complex64. */
+/* FP64 iterative refinement of a solve whose factors are complex64 (or
+ * complex128).  d_report (optional, device, [batch] harp_refine_report,
+ * caller-owned) receives the per-system report on the device. */
 typedef struct {
     const void *d_Z;     /* complex128 matrices the residual is taken against */
     int64_t ldz;
     int64_t stride_z;
     double tol;          /* stop when ||B - Z X||_F <= tol ||Z||_F ||X||_F */
     int32_t max_iter;    /* maximum number of correction sweeps (>= 0) */
+    void *d_report;      /* optional device copy of the report (NULL: none) */
 } harp_refine;
 
 typedef struct {
@@ -293,13 +296,23 @@ harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype 
  * reduced_factor (dtype as factored): per group of 256 rows, the group's row
  * exchanges, the inverse unit-lower block and the update of the rows below;
  * then per group backwards, the inverse upper block and the update of the rows
- * above, all products on the matrix cores.  B and X are complex128 (n x nrhs).  With refine ==
- * NULL, X is the solve in the factor precision.  With refine != NULL: the
- * residual R = B - Z X is formed in FP64 against refine->d_Z, corrections
- * are solved with the factors and added in FP64, until the tolerance or
- * max_iter; this path synchronises the stream once per sweep, and, if
- * report != NULL (host, [batch]), fills it.  Returns HARP_E_NOCONV if a
- * system missed the tolerance. */
+ * above, all products on the matrix cores.  B and X are complex128 (n x nrhs).
+ * With refine == NULL, X is the solve in the factor precision.  With refine !=
+ * NULL: the residual R = B - Z X is formed in FP64 against refine->d_Z and
+ * corrections are solved with the factors and added in FP64, until the
+ * tolerance or max_iter sweeps.  The convergence test runs on the device: a
+ * system that meets the tolerance (or exhausts max_iter) is skipped by every
+ * later kernel.
+ *   report != NULL (host, [batch]): the call synchronises the stream once
+ *     after the first correction and once after each further sweep while some
+ *     system still needs one, fills the report, and returns HARP_E_NOCONV if a
+ *     system missed the tolerance.
+ *   report == NULL: nothing synchronises (the call may be captured in a HIP
+ *     graph); all max_iter sweeps are enqueued, converged systems skipping
+ *     them; the report is left on the device (refine->d_report, when given)
+ *     and the call returns HARP_OK.
+ * Kernels of this call read and write d_ws; concurrent calls need separate
+ * workspaces. */
 harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
                           const void *d_LU, int64_t lda, int64_t stride_lu, const int32_t *d_ipiv,
                           const void *d_aux, size_t aux_bytes, const void *d_B, int64_t ldb, int64_t stride_b, void *d_X, int64_t ldx,

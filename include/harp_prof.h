@@ -41,6 +41,11 @@ typedef enum {
 /* on != 0: clear the records and start recording; on == 0: stop. */
 harp_status harp_prof_enable(int32_t on);
 
+/* Stop recording and destroy the pooled events (call before the HIP runtime
+ * shuts down, e.g. from an interpreter exit hook; the library keeps no
+ * static object whose destructor would do it at process exit). */
+harp_status harp_prof_release(void);
+
 /* Totals of one class: launches, summed event time (ms), flops, bytes. */
 harp_status harp_prof_read(int32_t cls, int64_t *launches, double *ms, double *flops, double *bytes);
 

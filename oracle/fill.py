@@ -47,13 +47,14 @@ def fill(model: Model, x, y, ri: float = 0.0) -> np.ndarray:
     Z = np.zeros((na, nm, na, nm), dtype=np.complex128)
     mm, nn = np.meshgrid(np.arange(na), np.arange(na), indexing="ij")
     off = mm != nn
+    if ri > 0.0:
+        # blocks of pairs beyond the radius of influence stay zero (not evaluated)
+        off &= np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :]) <= ri
     Rx = (x[:, None] - x[None, :])[off]
     Ry = (y[:, None] - y[None, :])[off]
     blocks = np.concatenate([eval_model(model, Rx[i:i + 32768], Ry[i:i + 32768])
                              for i in range(0, Rx.size, 32768)] or
                             [np.zeros((0, nm, nm), dtype=np.complex128)])
-    if ri > 0.0:
-        blocks[np.hypot(Rx, Ry) > ri] = 0.0
     Z[mm[off], :, nn[off], :] = blocks
     for m in range(na):
         Z[m, :, m, :] = model.Z_self

@@ -5,6 +5,7 @@ no fallback: if the shared object is missing, every entry point raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
@@ -30,7 +31,7 @@ class HarpElement(ctypes.Structure):
 
 class HarpRefine(ctypes.Structure):
     _fields_ = [("d_Z", c_vp), ("ldz", c_i64), ("stride_z", c_i64), ("tol", c_dbl),
-                ("max_iter", c_i32)]
+                ("max_iter", c_i32), ("d_report", c_vp)]
 
 
 class HarpRefineReport(ctypes.Structure):
@@ -89,6 +90,7 @@ SIGNATURES = {
 # (include/harp_prof.h); neither is part of the solver boundary
 DEBUG_SIGNATURES = {
     "harp_prof_enable": (c_i32, [c_i32]),
+    "harp_prof_release": (c_i32, []),
     "harp_prof_read": (c_i32, [c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
     "harp_debug_cgemm": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_vp, c_i64, c_i64, c_vp,
@@ -110,6 +112,8 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        # pooled profiler events are destroyed while the HIP runtime is alive
+        atexit.register(L.harp_prof_release)
     return _lib
 
 

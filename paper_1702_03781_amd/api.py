@@ -18,9 +18,12 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import HarpElement, HarpRefine, HarpRefineReport, check, lib
+from ._lib import HarpElement, HarpError, HarpRefine, HarpRefineReport, check, lib
 
 C64, C128 = 0, 1
+# status codes of include/harp.h raised by the binding after reading the
+# device-side outcome flags
+HARP_E_ARG, HARP_E_DOMAIN, HARP_E_SINGULAR = -1, -2, -3
 _DT = {"c64": C64, "c128": C128, torch.complex64: C64, torch.complex128: C128}
 _TORCH_DT = {C64: torch.complex64, C128: torch.complex128}
 
@@ -54,6 +57,31 @@ def _cm(M: torch.Tensor, name: str):
     return _ptr(M), ld, stride
 
 
+def check_flags(fill_info=None, factor_info=None, where: str = "") -> None:
+    """Raise the library's numerical outcomes as errors (reads the device
+    flags, so it waits for the work that writes them).  fill_info: pairs
+    closer than the model's inner radius r_min (HARP_E_DOMAIN), or -1 / -2 for
+    a model or descriptor that does not match (HARP_E_ARG); factor_info: the
+    1-based index of an exact zero pivot (HARP_E_SINGULAR)."""
+    def host(v):
+        return v.detach().cpu().numpy().ravel() if hasattr(v, "detach") else np.asarray(v).ravel()
+
+    if fill_info is not None:
+        fi = host(fill_info)
+        if (fi < 0).any():
+            raise HarpError(HARP_E_ARG, f"{where}: model or system descriptor mismatch "
+                                        f"(entries {np.flatnonzero(fi < 0).tolist()})")
+        if (fi > 0).any():
+            raise HarpError(HARP_E_DOMAIN, f"{where}: {int(fi.sum())} antenna pair(s) closer than the "
+                                           f"model's r_min (matrices {np.flatnonzero(fi > 0).tolist()})")
+    if factor_info is not None:
+        ii = host(factor_info)
+        if (ii > 0).any():
+            b = int(np.flatnonzero(ii > 0)[0])
+            raise HarpError(HARP_E_SINGULAR, f"{where}: exact zero pivot at column {int(ii[b]) - 1} "
+                                             f"of matrix {b}")
+
+
 # --------------------------------------------------------------------------
 # models
 # --------------------------------------------------------------------------
@@ -71,6 +99,10 @@ class Model:
     Q: int
     freq: float
     r_min: float
+    # reciprocity of the table (C^{ST}_p = (-1)^p C^{TS}_p, Z_self = Z_self^T),
+    # which makes the filled matrix complex-symmetric; harp_fit guarantees it
+    # (even angular grid), pack_model measures it
+    reciprocal: bool = True
 
     @property
     def nbytes(self) -> int:
@@ -137,7 +169,110 @@ def pack_model(C: np.ndarray, Z_self: np.ndarray, w: np.ndarray, samples: np.nda
     put(off_port, w.astype(np.complex128))
     put(off_samples, samples.astype(np.float64))
     blob = torch.from_numpy(buf).to(device)
-    return Model(blob, n_mbf, n_samp, P, Q, float(freq), float(r_min))
+    return Model(blob, n_mbf, n_samp, P, Q, float(freq), float(r_min), _table_reciprocal(C, Z_self))
+
+
+def _table_reciprocal(C: np.ndarray, Z_self: np.ndarray) -> bool:
+    """C^{ST}_pq = (-1)^p C^{TS}_pq and Z_self = Z_self^T (to rounding of a fit)."""
+    P = (C.shape[2] - 1) // 2
+    sign = (-1.0) ** np.arange(-P, P + 1)
+    scale = max(float(np.abs(C).max()), 1e-300)
+    return bool(np.abs(np.swapaxes(C, 0, 1) - sign[None, None, :, None] * C).max() <= 1e-8 * scale and
+                np.abs(Z_self - Z_self.T).max() <= 1e-12 * max(float(np.abs(Z_self).max()), 1e-300))
+
+
+# --------------------------------------------------------------------------
+# persisted models (a model is built once per element and frequency and
+# reused for every layout, Section III-C)
+# --------------------------------------------------------------------------
+
+_FILE_MAGIC = b"HARPMODL"
+_FILE_VERSION = 1
+_FILE_HDR = struct.Struct("<8sII32sQ")   # magic, file version, blob version, element hash, blob bytes
+
+
+def element_hash(samples: np.ndarray, wire_radius: float) -> bytes:
+    """SHA-256 of an element description: the [n_mbf][n_samp][8] float64
+    sample records (little-endian) and the wire radius."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(samples, dtype="<f8").tobytes())
+    h.update(struct.pack("<d", float(wire_radius)))
+    return h.digest()
+
+
+def _blob_element_hash(raw: np.ndarray) -> bytes:
+    vals = _HDR.unpack(bytes(raw[:_HDR.size]))
+    nm, ns, wire, off_s = vals[2], vals[3], vals[12], vals[17]
+    samples = raw[off_s:off_s + nm * ns * 8 * 8].view("<f8").reshape(nm, ns, 8)
+    return element_hash(samples, wire)
+
+
+def save_model(model: Model, path: str) -> None:
+    """Write a model blob to `path`: a 56-byte file header (magic "HARPMODL",
+    file version, blob version, SHA-256 of the element the blob was built
+    from, blob size) followed by the blob bytes exactly as the library reads
+    them."""
+    raw = model.blob.detach().cpu().numpy()
+    vals = _HDR.unpack(bytes(raw[:_HDR.size]))
+    if vals[0] != 0x50524148:
+        raise ValueError("save_model: not a model blob (bad magic)")
+    hdr = _FILE_HDR.pack(_FILE_MAGIC, _FILE_VERSION, vals[1], _blob_element_hash(raw), raw.size)
+    with open(path, "wb") as f:
+        f.write(hdr)
+        f.write(raw.tobytes())
+
+
+def load_model(path: str, device="cuda", samples: np.ndarray | None = None,
+               wire_radius: float | None = None) -> Model:
+    """Read a file written by save_model.  Checks the file magic and version,
+    the blob's own magic, version and size, and that the element samples the
+    blob carries hash to the recorded element hash; when `samples` (and
+    `wire_radius`) are given, also that the file was built from that element.
+    Raises ValueError on any mismatch."""
+    with open(path, "rb") as f:
+        head = f.read(_FILE_HDR.size)
+        if len(head) != _FILE_HDR.size:
+            raise ValueError(f"load_model: {path}: truncated header")
+        magic, fver, bver, ehash, nbytes = _FILE_HDR.unpack(head)
+        if magic != _FILE_MAGIC:
+            raise ValueError(f"load_model: {path}: not a HARP model file")
+        if fver != _FILE_VERSION:
+            raise ValueError(f"load_model: {path}: file version {fver}, expected {_FILE_VERSION}")
+        raw = np.frombuffer(f.read(), dtype=np.uint8)
+    if raw.size != nbytes or raw.size < _HDR.size:
+        raise ValueError(f"load_model: {path}: blob of {raw.size} bytes, header says {nbytes}")
+    vals = _HDR.unpack(bytes(raw[:_HDR.size]))
+    keys = ["magic", "version", "n_mbf", "n_samp", "P", "Q", "n_alpha", "n_t", "freq_hz", "k",
+            "omega_mu", "r_min", "wire_radius", "off_coef", "off_coef32", "off_self", "off_port",
+            "off_samples", "total_bytes"]
+    h = dict(zip(keys, vals))
+    if h["magic"] != 0x50524148 or h["version"] != bver or bver != 1:
+        raise ValueError(f"load_model: {path}: blob magic / version mismatch")
+    if h["total_bytes"] != raw.size or model_layout_bytes(h["n_mbf"], h["n_samp"], h["P"], h["Q"]) != raw.size:
+        raise ValueError(f"load_model: {path}: blob size does not match its header")
+    if _blob_element_hash(raw) != ehash:
+        raise ValueError(f"load_model: {path}: element samples do not match the recorded hash")
+    if samples is not None:
+        wr = h["wire_radius"] if wire_radius is None else wire_radius
+        if element_hash(samples, wr) != ehash:
+            raise ValueError(f"load_model: {path}: built from a different element")
+    nm, P, Q = h["n_mbf"], h["P"], h["Q"]
+    nc = nm * nm * (2 * P + 1) * (Q + 1)
+    C = raw[h["off_coef"]:h["off_coef"] + nc * 16].view(np.complex128).reshape(nm, nm, 2 * P + 1, Q + 1)
+    Zs = raw[h["off_self"]:h["off_self"] + nm * nm * 16].view(np.complex128).reshape(nm, nm)
+    blob = torch.from_numpy(raw.copy()).to(device)
+    return Model(blob, nm, h["n_samp"], P, Q, float(h["freq_hz"]), float(h["r_min"]), _table_reciprocal(C, Zs))
+
+
+def model_layout_bytes(n_mbf: int, n_samp: int, P: int, Q: int) -> int:
+    """Size of a model blob (host arithmetic of the layout in include/harp.h;
+    equals harp_model_bytes)."""
+    def a256(b):
+        return (b + 255) & ~255
+    ncoef = n_mbf * n_mbf * (2 * P + 1) * (Q + 1)
+    return (256 + a256(ncoef * 16) + a256(ncoef * 8) + a256(n_mbf * n_mbf * 16) + a256(n_mbf * 16)
+            + a256(n_mbf * n_samp * 8 * 8))
 
 
 @dataclass
@@ -205,9 +340,12 @@ def model_arrays(model: Model) -> dict:
 
 def harp_fill(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, dtype="c64", ri: float = 0.0,
               Z: torch.Tensor | None = None, Z32: torch.Tensor | None = None,
-              dual: bool = False):
+              dual: bool = False, check_domain: bool = True):
     """Fill the reduced matrices of all frequencies (Eq. 4).  Returns (Z, Z32,
-    info); Z32 is the complex64 copy when dual=True (dtype must be c128)."""
+    info); Z32 is the complex64 copy when dual=True (dtype must be c128).
+    With check_domain (default) the call waits for the fill and raises
+    HARP_E_DOMAIN if a pair is closer than the model's r_min (HARP_E_ARG for a
+    model that does not match); otherwise info holds the counts."""
     dt = _DT[dtype]
     dev = models.data.device
     n_ant = int(x.numel())
@@ -224,6 +362,8 @@ def harp_fill(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, dtype="c64",
     check(lib().harp_fill(_ptr(models.data), models.stride, models.n_freq, models.n_mbf,
                           models.Q, models.p_max, _ptr(x), _ptr(y), n_ant, float(ri), dt,
                           pz, ldz, sz, p32, ld32, s32, _ptr(info), _stream(dev)), "harp_fill")
+    if check_domain:
+        check_flags(fill_info=info, where="harp_fill")
     return Z, Z32, info
 
 
@@ -266,8 +406,11 @@ class Factors:
         return iter((self.ipiv, self.info))
 
 
-def reduced_factor(A: torch.Tensor) -> Factors:
-    """In-place LU with partial pivoting of a batch of column-major matrices."""
+def reduced_factor(A: torch.Tensor, check_singular: bool = True) -> Factors:
+    """In-place LU with partial pivoting of a batch of column-major matrices.
+    With check_singular (default) the call waits for the factorisation and
+    raises HARP_E_SINGULAR on an exact zero pivot; otherwise F.info holds the
+    pivot indices (LAPACK's info convention)."""
     if A.dim() == 2:
         A = A.unsqueeze(0)
     dt = _DT[A.dtype]
@@ -280,14 +423,19 @@ def reduced_factor(A: torch.Tensor) -> Factors:
     aux = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=A.device)
     check(lib().reduced_factor(n, b, dt, pa, lda, sa, _ptr(ipiv), _ptr(info), _ptr(aux),
                                ws_b.value, _stream(A.device)), "reduced_factor")
+    if check_singular:
+        check_flags(factor_info=info, where="reduced_factor")
     return Factors(A, ipiv, info, aux)
 
 
 def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
                   Z64: torch.Tensor | None = None, tol: float = 1e-12, max_iter: int = 10,
-                  raise_noconv: bool = True):
+                  raise_noconv: bool = True, device_report: bool = False):
     """Solve with the factors of reduced_factor; optional FP64 refinement
-    against Z64.  Returns (X, reports or None)."""
+    against Z64.  Returns (X, reports or None).  device_report=True: the
+    refinement runs without any host synchronisation (all max_iter sweeps
+    enqueued, converged systems skipping them) and the second value is the
+    device array of reports (read it with read_reports after the stream)."""
     LU = F.LU
     if B.dim() == 2:
         B = B.unsqueeze(0)
@@ -301,10 +449,13 @@ def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
     px, ldx, sx = _cm(X, "X")
     ref = None
     rep = None
+    rep_dev = None
     if Z64 is not None:
         pz, ldz, sz = _cm(Z64, "Z64")
-        ref = HarpRefine(pz, ldz, sz, float(tol), int(max_iter))
-        rep = (HarpRefineReport * b)()
+        if device_report:
+            rep_dev = torch.zeros(b * 16, dtype=torch.uint8, device=LU.device)
+        ref = HarpRefine(pz, ldz, sz, float(tol), int(max_iter), _ptr(rep_dev))
+        rep = None if device_report else (HarpRefineReport * b)()
     ws_b = ctypes.c_size_t()
     check(lib().reduced_solve_ws(n, nrhs, b, dt, int(ref is not None), ctypes.byref(ws_b)),
           "reduced_solve_ws")
@@ -314,14 +465,22 @@ def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
                              ctypes.byref(ref) if ref is not None else None,
                              rep if rep is not None else None, _ptr(ws), ws_b.value,
                              _stream(LU.device))
+    X._keep = ws   # the workspace lives until the solution is used
     if st == -4 and not raise_noconv:
         st = 0
     check(st, "reduced_solve")
+    if device_report:
+        return X, rep_dev
     reports = None
     if rep is not None:
         reports = [{"iters": r.iters, "converged": bool(r.converged), "resid_rel": r.resid_rel}
                    for r in rep]
     return X, reports
+
+
+def read_reports(rep_dev: torch.Tensor):
+    """Refinement reports from a device report array (waits for the stream)."""
+    return _reports_from_device(rep_dev)
 
 
 # --------------------------------------------------------------------------
@@ -450,10 +609,16 @@ class ArrayResponse(torch.autograd.Function):
     right-hand side per port, and Eqs. 5-6.  The backward pass is the
     hand-written adjoint: the patterns' and ports' vector-Jacobian products,
     one adjoint solve with the same factors (Z is complex-symmetric), the
-    cotangent of Z as the product -conj(Lambda) X^T, and the fill's product."""
+    cotangent of Z as the product -conj(Lambda) X^T, and the fill's product.
+    The forward pass raises HARP_E_DOMAIN for a pair closer than the model's
+    r_min (e.g. an optimiser step that brings two elements too close) and
+    HARP_E_SINGULAR for an exact zero pivot."""
 
     @staticmethod
     def forward(ctx, x, y, model, theta, phi, ri):
+        if not model.reciprocal:
+            raise ValueError("array_response: the adjoint solves with Z instead of Z^T, which needs a "
+                             "reciprocal model table (C^{ST}_p = (-1)^p C^{TS}_p, symmetric self block)")
         mb = stack_models([model])
         x64 = x.detach().to(torch.float64).contiguous()
         y64 = y.detach().to(torch.float64).contiguous()
@@ -507,6 +672,7 @@ __all__ = [
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
     "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
+    "save_model", "load_model", "read_reports", "element_hash", "check_flags", "HarpError",
     "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "autotune_batch_costs", "harp_fill_systems", "harp_port_rhs_systems",
     "harp_port_admittance_systems", "BatchSolver", "StationSolver", "Cell", "harp_tessellate",
     "TessellatedSolver",
@@ -523,13 +689,16 @@ class StationSolver:
 
     mode "refined": FP64 fill written as complex128 (residual matrix) and as
     its complex64 rounding (factored on the matrix cores), complex64 solve,
-    FP64 iterative refinement to `tol`.
+    FP64 iterative refinement to `tol` (convergence decided on the device;
+    the host waits once, after the first correction, in the common case).
     mode "plain": complex128 fill, factor and solve (the FP64 reference path).
+    ri > 0: radius of influence of the fill (blocks of pairs farther apart are
+    zero, Section II-D).
     """
 
     def __init__(self, models: ModelBatch, x: torch.Tensor, y: torch.Tensor, mode="refined",
-                 tol: float = 1e-10, max_iter: int = 10):
-        self.models, self.mode, self.tol, self.max_iter = models, mode, tol, max_iter
+                 tol: float = 1e-10, max_iter: int = 10, ri: float = 0.0):
+        self.models, self.mode, self.tol, self.max_iter, self.ri = models, mode, tol, max_iter, float(ri)
         dev = models.data.device
         self.x = x.contiguous()
         self.y = y.contiguous()
@@ -541,8 +710,9 @@ class StationSolver:
         self.B = colmajor(nf, n, self.n_ant, torch.complex128, dev)
         self.X = colmajor(nf, n, self.n_ant, torch.complex128, dev)
         self.Y = colmajor(nf, self.n_ant, self.n_ant, torch.complex128, dev)
-        self.info = torch.empty(nf, dtype=torch.int32, device=dev)
-        self.finfo = torch.empty(nf, dtype=torch.int32, device=dev)
+        # fill domain counts (row 0) and zero-pivot indices (row 1), read together
+        self.flags = torch.zeros((2, nf), dtype=torch.int32, device=dev)
+        self.info, self.finfo = self.flags[0], self.flags[1]
         self.ipiv = torch.empty((nf, n), dtype=torch.int32, device=dev)
         dt = C64 if mode == "refined" else C128
         aux_b = ctypes.c_size_t()
@@ -556,11 +726,13 @@ class StationSolver:
         self.ws_bytes = ws_b.value
         self.reports = None
 
-    def step(self, events=None):
+    def step(self, events=None, check_flags_: bool = True):
         """One pass of the hot path.  events: optional five torch.cuda.Event
         recorded on the stream at the phase boundaries (start, after fill and
         excitation, after the factorisation, after the solve and refinement,
-        after the admittances)."""
+        after the admittances).  With check_flags_ (default) the fill's domain
+        counts and the factorisation's zero pivots are read at the end and
+        raised (HARP_E_DOMAIN, HARP_E_SINGULAR)."""
         L = lib()
         mb, n, na, nf = self.models, self.n, self.n_ant, self.models.n_freq
         st = _stream(mb.data.device)
@@ -570,7 +742,7 @@ class StationSolver:
         pz, ldz, sz = _cm(self.Z64, "Z64")
         p32, ld32, s32 = _cm(self.Z32, "Z32") if refined else (0, 0, 0)
         check(L.harp_fill(_ptr(mb.data), mb.stride, nf, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
-                          _ptr(self.y), na, 0.0, C128, pz, ldz, sz, p32, ld32, s32,
+                          _ptr(self.y), na, self.ri, C128, pz, ldz, sz, p32, ld32, s32,
                           _ptr(self.info), st), "harp_fill")
         pb, ldb, sb = _cm(self.B, "B")
         check(L.harp_port_rhs(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, pb, ldb, sb, st),
@@ -584,10 +756,12 @@ class StationSolver:
         px, ldx, sx = _cm(self.X, "X")
         ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter)) if refined else None
         rep = (HarpRefineReport * nf)() if refined else None
-        check(L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.aux),
-                              self.aux_bytes, pb, ldb, sb, px, ldx,
-                              sx, ctypes.byref(ref) if ref is not None else None, rep,
-                              _ptr(self.ws), self.ws_bytes, st), "reduced_solve")
+        status = L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.aux),
+                                 self.aux_bytes, pb, ldb, sb, px, ldx,
+                                 sx, ctypes.byref(ref) if ref is not None else None, rep,
+                                 _ptr(self.ws), self.ws_bytes, st)
+        if status not in (0, -4):          # argument / workspace / runtime errors: nothing more to enqueue
+            check(status, "reduced_solve")
         mark(3)
         py, ldy, sy = _cm(self.Y, "Y")
         check(L.harp_port_admittance(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, px, ldx, sx, py,
@@ -596,6 +770,10 @@ class StationSolver:
         if rep is not None:
             self.reports = [{"iters": r.iters, "converged": bool(r.converged),
                              "resid_rel": r.resid_rel} for r in rep]
+        if check_flags_:
+            fl = self.flags.cpu().numpy()
+            check_flags(fl[0], fl[1], "StationSolver.step")
+        check(status, "reduced_solve")
         return self.X, self.Y
 
 
@@ -636,8 +814,9 @@ def harp_batch_plan(n_ant, n_mbf: int, pad_multiple: int = 8, max_order: int = 8
 
 def harp_fill_systems(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, sys: torch.Tensor,
                       n_ant_pad: int, dtype="c128", ri: float = 0.0, Z: torch.Tensor | None = None,
-                      Z32: torch.Tensor | None = None, dual: bool = False):
-    """Fill a group of systems padded to n_ant_pad antennas.  Returns (Z, Z32, info)."""
+                      Z32: torch.Tensor | None = None, dual: bool = False, check_domain: bool = True):
+    """Fill a group of systems padded to n_ant_pad antennas.  Returns (Z, Z32,
+    info); check_domain as for harp_fill."""
     dt = _DT[dtype]
     dev = models.data.device
     n_sys = sys.numel() // SYSTEM_DTYPE.itemsize
@@ -654,6 +833,8 @@ def harp_fill_systems(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, sys:
                                   models.p_max, _ptr(x), _ptr(y), int(x.numel()), _ptr(sys), n_sys, n_ant_pad,
                                   float(ri), dt, pz, ldz, sz, p32, ld32, s32, _ptr(info), _stream(dev)),
           "harp_fill_systems")
+    if check_domain:
+        check_flags(fill_info=info, where="harp_fill_systems")
     return Z, Z32, info
 
 
@@ -690,9 +871,11 @@ def harp_port_admittance_systems(models: ModelBatch, sys: torch.Tensor, X: torch
 
 
 class _Group:
-    """Device buffers of one padded group (refined path)."""
+    """Device buffers of one padded group (refined path).  info / finfo are
+    views into the batch's shared flag array."""
 
-    def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, n_ports, pad_multiple, dev):
+    def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, n_ports, pad_multiple, dev,
+                 flags, off):
         self.members, self.n_pad = members, n_pad
         c = len(members)
         n = self.n = n_pad * models.n_mbf
@@ -706,14 +889,25 @@ class _Group:
         self.B = colmajor(c, n, npp, torch.complex128, dev)
         self.X = colmajor(c, n, npp, torch.complex128, dev)
         self.Y = colmajor(c, n_pad, npp, torch.complex128, dev)
-        self.info = torch.empty(c, dtype=torch.int32, device=dev)
-        self.finfo = torch.empty(c, dtype=torch.int32, device=dev)
+        self.info = flags[0, off:off + c]
+        self.finfo = flags[1, off:off + c]
         self.ipiv = torch.empty((c, n), dtype=torch.int32, device=dev)
+        # refinement report on the device (harp_refine_report, 16 bytes each)
+        self.rep_dev = torch.zeros(c * 16, dtype=torch.uint8, device=dev)
         b = ctypes.c_size_t()
         check(lib().reduced_factor_ws(n, c, C64, ctypes.byref(b)), "reduced_factor_ws")
         self.aux, self.aux_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
         check(lib().reduced_solve_ws(n, npp, c, C64, 1, ctypes.byref(b)), "reduced_solve_ws")
         self.ws, self.ws_bytes = torch.empty(max(1, b.value), dtype=torch.uint8, device=dev), b.value
+
+
+_REPORT_DTYPE = np.dtype([("iters", "<i4"), ("converged", "<i4"), ("resid_rel", "<f8")])
+
+
+def _reports_from_device(rep_dev: torch.Tensor):
+    a = rep_dev.cpu().numpy().view(_REPORT_DTYPE)
+    return [{"iters": int(r["iters"]), "converged": bool(r["converged"]), "resid_rel": float(r["resid_rel"])}
+            for r in a]
 
 
 def autotune_batch_costs(models: ModelBatch, sizes=(96, 256, 480), counts=(1, 8), reps: int = 2,
@@ -766,12 +960,20 @@ class BatchSolver:
     indices, n_ports): its ports are its first n_ports antennas (default all).
     Systems are grouped by harp_batch_plan and padded per group; groups are
     issued round-robin on `streams` HIP streams (default priority), all
-    buffers allocated once."""
+    buffers allocated once.
+
+    graph=False: each group's refinement reports to the host (one
+    synchronisation per group in the common case).  graph=True: the whole
+    step -- every group's fill, excitation, factorisation, solve with a
+    device-controlled refinement of at most `sweeps` corrections, and
+    admittances -- is captured once as one HIP graph and replayed; nothing
+    synchronises inside a step and the reports are read from the device."""
 
     def __init__(self, models: ModelBatch, layouts, tol: float = 1e-10, max_iter: int = 10,
-                 streams: int = 1, ri: float = 0.0, **plan_kw):
+                 streams: int = 1, ri: float = 0.0, graph: bool = False, sweeps: int = 3, **plan_kw):
         dev = models.data.device
         self.models, self.tol, self.max_iter, self.ri = models, tol, max_iter, ri
+        self.graph_mode, self.sweeps = graph, sweeps
         xs, ys, model_idx, n_ant, pos, n_ports, self.layout_of = [], [], [], [], [], [], []
         off = 0
         for li, lay in enumerate(layouts):
@@ -793,14 +995,18 @@ class BatchSolver:
         self.n_ant, self.n_ports = n_ant, n_ports
         order, groups = harp_batch_plan(n_ant, models.n_mbf, **plan_kw)
         pm = plan_kw.get("pad_multiple", 8)
-        self.groups = [_Group(models, order[b:e], pad, model_idx, n_ant, pos, n_ports, pm, dev)
-                       for b, e, pad in groups]
+        self.flags = torch.zeros((2, len(n_ant)), dtype=torch.int32, device=dev)
+        self.groups = []
+        for b, e, pad in groups:
+            self.groups.append(_Group(models, order[b:e], pad, model_idx, n_ant, pos, n_ports, pm, dev,
+                                      self.flags, b))
         self.where = {}
         for gi, g in enumerate(self.groups):
             for k, s in enumerate(g.members):
                 self.where[s] = (gi, k)
-        self.streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(streams - 1)]
-        self.reports = None
+        self.streams = [torch.cuda.Stream(dev) for _ in range(streams - 1)]
+        self._reports = None
+        self._graph = None
 
     @property
     def n_systems(self) -> int:
@@ -820,47 +1026,76 @@ class BatchSolver:
         check(L.reduced_factor(g.n, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.finfo), _ptr(g.aux),
                                g.aux_bytes, st), "reduced_factor")
 
-    def _back(self, g: _Group, st: int):
+    def _back(self, g: _Group, st: int, host: bool):
         L, mb = lib(), self.models
         c = len(g.members)
         pz, ldz, sz = _cm(g.Z64, "Z64")
         p32, ld32, s32 = _cm(g.Z32, "Z32")
         pb, ldb, sb = _cm(g.B, "B")
         px, ldx, sx = _cm(g.X, "X")
-        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter))
-        rep = (HarpRefineReport * c)()
-        check(L.reduced_solve(g.n, g.n_ports_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux), g.aux_bytes,
-                              pb, ldb, sb, px, ldx, sx, ctypes.byref(ref), rep, _ptr(g.ws), g.ws_bytes, st),
-              "reduced_solve")
+        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter if host else self.sweeps),
+                         _ptr(g.rep_dev))
+        rep = (HarpRefineReport * c)() if host else None
+        status = L.reduced_solve(g.n, g.n_ports_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux),
+                                 g.aux_bytes, pb, ldb, sb, px, ldx, sx, ctypes.byref(ref), rep, _ptr(g.ws),
+                                 g.ws_bytes, st)
+        if status not in (0, -4):
+            check(status, "reduced_solve")
         py, ldy, sy = _cm(g.Y, "Y")
         check(L.harp_port_admittance_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c,
                                              g.n_pad, g.n_ports_pad, px, ldx, sx, py, ldy, sy, st),
               "harp_port_admittance_systems")
-        return rep
+        return status
 
-    def step(self):
+    def _enqueue(self, host: bool):
+        """Every group's work on the current stream and the side streams
+        (forked from and joined back into the current stream)."""
+        main = torch.cuda.current_stream(self.models.data.device)
+        sts = [main] + self.streams
+        for s in self.streams:
+            s.wait_stream(main)
+        for gi, g in enumerate(self.groups):
+            self._front(g, sts[gi % len(sts)].cuda_stream)
+        noconv = False
+        for gi, g in enumerate(self.groups):
+            noconv |= self._back(g, sts[gi % len(sts)].cuda_stream, host) == -4
+        for s in self.streams:
+            main.wait_stream(s)
+        return noconv
+
+    def step(self, check_flags_: bool = True):
         """One pass over every system.  Fill, excitation and factorisation of
-        all groups are enqueued first; the solves (which synchronise their
-        stream once per refinement sweep) follow group by group."""
-        sts = [s.cuda_stream for s in self.streams]
-        if len(self.streams) > 1:
-            ev = torch.cuda.Event()
-            ev.record(self.streams[0])
-            for s in self.streams[1:]:
-                s.wait_event(ev)
-        for gi, g in enumerate(self.groups):
-            self._front(g, sts[gi % len(sts)])
-        reports = [None] * self.n_systems
-        for gi, g in enumerate(self.groups):
-            rep = self._back(g, sts[gi % len(sts)])
-            for k, s in enumerate(g.members):
-                reports[s] = {"iters": rep[k].iters, "converged": bool(rep[k].converged),
-                              "resid_rel": rep[k].resid_rel}
-        for s in self.streams[1:]:
-            ev = torch.cuda.Event()
-            ev.record(s)
-            self.streams[0].wait_event(ev)
-        self.reports = reports
+        all groups are enqueued first, then the solves and admittances.  With
+        check_flags_ (default) the domain counts and zero pivots of every
+        system are read at the end and raised (HARP_E_DOMAIN,
+        HARP_E_SINGULAR)."""
+        self._reports = None
+        if self.graph_mode:
+            if self._graph is None:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    self._enqueue(host=False)
+                self._graph = g
+            self._graph.replay()
+            noconv = False
+        else:
+            noconv = self._enqueue(host=True)
+        if check_flags_:
+            fl = self.flags.cpu().numpy()
+            check_flags(fl[0], fl[1], "BatchSolver.step")
+        if noconv:
+            raise HarpError(-4, "BatchSolver.step: refinement did not converge")
+
+    @property
+    def reports(self):
+        """Refinement report of every system (read from the device)."""
+        if self._reports is None:
+            reports = [None] * self.n_systems
+            for g in self.groups:
+                for k, r in enumerate(_reports_from_device(g.rep_dev)):
+                    reports[g.members[k]] = r
+            self._reports = reports
+        return self._reports
 
     def system(self, s: int):
         """(X, Y, fill info, factor info) of system s, unpadded views: X is

@@ -1023,12 +1023,19 @@ __global__ void __launch_bounds__(256) axpy_kernel(double2* __restrict__ X, int6
     }
 }
 
-// sum of |v|^2 over a column-major complex128 matrix: per-block partials
+// sum of |v|^2 over column-major complex128 matrices: per-block partials.
+// blockIdx.y selects the matrix (0: M0, 1: M1), so the residual and the
+// solution of a refinement sweep take one launch; matrices whose `active`
+// flag is 0 are skipped.
 constexpr int kNormBlocks = 64;
-__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M, int64_t ld, int64_t s,
-                                                            int rows, int cols, double* __restrict__ part) {
-    const int b = blockIdx.z;
-    M += size_t(b) * s;
+__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M0, int64_t ld0, int64_t s0,
+                                                            const double2* __restrict__ M1, int64_t ld1, int64_t s1,
+                                                            int rows, int cols, double* __restrict__ part,
+                                                            const int32_t* __restrict__ active) {
+    const int b = blockIdx.z, which = blockIdx.y;
+    if (active && active[b] == 0) return;
+    const double2* M = which ? M1 + size_t(b) * s1 : M0 + size_t(b) * s0;
+    const int64_t ld = which ? ld1 : ld0;
     double acc = 0.0;
     const int chunks = (rows + 255) / 256, units = chunks * cols;   // as in convert_kernel
     for (int u = blockIdx.x; u < units; u += gridDim.x) {
@@ -1041,14 +1048,52 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __res
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) part[size_t(b) * kNormBlocks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0)
+        part[(size_t(b) * 2 + which) * kNormBlocks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
+// partials of matrix 0 -> Frobenius norm (fixed summation order)
 __global__ void sumsq_final_kernel(const double* __restrict__ part, double* __restrict__ out, int batch) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     double s = 0.0;
-    for (int i = 0; i < kNormBlocks; ++i) s += part[size_t(b) * kNormBlocks + i];
+    for (int i = 0; i < kNormBlocks; ++i) s += part[size_t(b) * 2 * kNormBlocks + i];
     out[b] = sqrt(s);
+}
+
+// Refinement control on the device.  Every system starts active with a
+// zero report; after each residual, the check below turns the norms into the
+// relative residual ||R||_F / (||Z||_F ||X||_F) and decides: converged
+// (inactive), out of sweeps (inactive), or one more correction (iteration
+// count + 1).  Kernels of the sweep skip inactive systems.
+__global__ void refine_init_kernel(int32_t* __restrict__ active, harp_refine_report* __restrict__ rep, int batch) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    active[b] = 1;
+    rep[b].iters = 0;
+    rep[b].converged = 0;
+    rep[b].resid_rel = 0.0;
+}
+__global__ void refine_check_kernel(const double* __restrict__ part, const double* __restrict__ znorm, int batch,
+                                    double tol, int max_iter, int32_t* __restrict__ active,
+                                    harp_refine_report* __restrict__ rep) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch || active[b] == 0) return;
+    double sr = 0.0, sx = 0.0;
+    for (int i = 0; i < kNormBlocks; ++i) {
+        sr += part[size_t(b) * 2 * kNormBlocks + i];
+        sx += part[(size_t(b) * 2 + 1) * kNormBlocks + i];
+    }
+    const double rn = sqrt(sr), denom = znorm[b] * sqrt(sx);
+    const double rel = denom > 0.0 ? rn / denom : (rn == 0.0 ? 0.0 : INFINITY);
+    rep[b].resid_rel = rel;
+    if (rel <= tol) {
+        rep[b].converged = 1;
+        active[b] = 0;
+    } else if (rep[b].iters >= max_iter) {
+        active[b] = 0;
+    } else {
+        rep[b].iters += 1;   // a correction follows
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,7 +1124,14 @@ template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
 template <typename T, int NT, int RPT, int W, int H>
 harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
     if constexpr (panel_fits_r<T, NT, RPT, W * H>()) {
-        HARP_PROF_EXT_LAUNCH(HARP_K_GETF2, st, 0.0, 0.0, (getf2_kernel<T, NT, RPT, W, H>), dim3(batch), dim3(NT),
+        // algorithmic work: the panel's own elimination (rank-1 updates of
+        // m rows x w columns) and the unit-lower solve of the w top rows of
+        // the outer block's columns to its right
+        const double m = double(pa.n - pa.j0), w = double(pa.w), right = double(pa.kend - pa.j0 - pa.w);
+        double fl = 0.0;
+        for (int c = 0; c < pa.w; ++c) fl += 8.0 * (m - c - 1.0) * (w - c - 1.0);
+        fl = double(batch) * (fl + 4.0 * w * (w - 1.0) * right);
+        HARP_PROF_EXT_LAUNCH(HARP_K_GETF2, st, fl, 0.0, (getf2_kernel<T, NT, RPT, W, H>), dim3(batch), dim3(NT),
                              0, pa);
         HARP_LAUNCH_CHECK();
         return HARP_OK;
@@ -1403,11 +1455,13 @@ harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t
     return HARP_OK;
 }
 
+// Frobenius norms of `batch` complex128 matrices into out[batch]
 harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, int batch, double* part, double* out,
                       hipStream_t st) {
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 1, batch), dim3(256), 0, st,
-                                        static_cast<const double2*>(M), ld, s, rows, cols, part));
+                                        static_cast<const double2*>(M), ld, s, static_cast<const double2*>(nullptr),
+                                        int64_t(0), int64_t(0), rows, cols, part, static_cast<const int32_t*>(nullptr)));
     HARP_LAUNCH_CHECK();
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(sumsq_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, part, out,
@@ -1420,9 +1474,10 @@ struct SolveWs {
     float2* B32;      // n x nrhs complex64 per matrix (ld n)
     double2* R;       // n x nrhs complex128 per matrix (ld n)
     void* Tm;         // SB x nrhs per matrix in the factor precision (group temp)
-    double* part;     // [batch][kNormBlocks]
-    double* norms;    // [3][batch]: ||Z||, ||R||, ||X||
+    double* part;     // [batch][2][kNormBlocks]
+    double* znorm;    // [batch]: ||Z||_F
     int32_t* active;  // [batch]
+    harp_refine_report* rep;   // [batch]
 };
 
 size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveWs* w, char* base) {
@@ -1438,9 +1493,10 @@ size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveW
     W.B32 = reinterpret_cast<float2*>(take((dtype == HARP_C64) ? mat * batch * 8 : 0));
     W.R = reinterpret_cast<double2*>(take(refine ? mat * batch * 16 : 0));
     W.Tm = take(int64_t(kSB) * nrhs * batch * (dtype == HARP_C64 ? 8 : 16));
-    W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * kNormBlocks * 8 : 0));
-    W.norms = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 3 * 8 : 0));
+    W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 2 * kNormBlocks * 8 : 0));
+    W.znorm = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 8 : 0));
     W.active = reinterpret_cast<int32_t*>(take(refine ? int64_t(batch) * 4 : 0));
+    W.rep = reinterpret_cast<harp_refine_report*>(take(refine ? int64_t(batch) * int64_t(sizeof(harp_refine_report)) : 0));
     return size_t(off);
 }
 
@@ -1550,13 +1606,24 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
     if ((s = solve_into(d_B, ldb, stride_b, nullptr, false)) != HARP_OK) return s;
     if (!ref) return HARP_OK;
 
-    // FP64 iterative refinement
-    std::vector<double> hn(3 * size_t(batch));
-    std::vector<int32_t> act(batch, 1), iters(batch, 0), conv(batch, 0);
-    std::vector<double> rel(batch, 0.0);
-    if ((s = fro_norms(refine->d_Z, refine->ldz, refine->stride_z, n, n, batch, W.part, W.norms, st)) != HARP_OK)
+    // FP64 iterative refinement, controlled on the device: each round takes
+    // the FP64 residual of the active systems, its norm and the check kernel,
+    // then (unless it is the last round) the correction solve.  With a host
+    // report the host looks at the active flags only from the second round
+    // on (the complex64 solve alone never meets an FP64 tolerance), so a
+    // system that converges after one correction costs a single
+    // synchronisation; without one nothing synchronises and the whole sweep
+    // budget is enqueued.
+    harp_refine_report* rep = refine->d_report ? static_cast<harp_refine_report*>(refine->d_report) : W.rep;
+    const bool host = report != nullptr;
+    std::vector<int32_t> act_h(host ? batch : 0);
+    const unsigned gb = unsigned((batch + 63) / 64);
+    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                     hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, batch));
+    HARP_LAUNCH_CHECK();
+    if ((s = fro_norms(refine->d_Z, refine->ldz, refine->stride_z, n, n, batch, W.part, W.znorm, st)) != HARP_OK)
         return s;
-    HARP_HIP_CHECK(hipMemcpyAsync(W.active, act.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
+    int n_act = batch;   // systems the host knows to be active (work accounting of the timers only)
     for (int it = 0;; ++it) {
         // R = B - Z X  (FP64, MFMA)
         GemmArgs<double> g;
@@ -1578,42 +1645,36 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
         g.alpha = -1.0;
         g.beta = 1.0;
         g.active = W.active;
-        int n_act = 0;
-        for (int b = 0; b < batch; ++b) n_act += act[b];
         if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
-        if ((s = fro_norms(W.R, n, mat, n, nrhs, batch, W.part, W.norms + batch, st)) != HARP_OK) return s;
-        if ((s = fro_norms(d_X, ldx, stride_x, n, nrhs, batch, W.part, W.norms + 2 * batch, st)) != HARP_OK) return s;
-        HARP_HIP_CHECK(hipMemcpyAsync(hn.data(), W.norms, sizeof(double) * 3 * batch, hipMemcpyDeviceToHost, st));
-        HARP_HIP_CHECK(hipStreamSynchronize(st));
-        int n_active = 0;
-        for (int b = 0; b < batch; ++b) {
-            if (!act[b]) continue;
-            const double denom = hn[b] * hn[2 * batch + b];
-            rel[b] = denom > 0.0 ? hn[batch + b] / denom : (hn[batch + b] == 0.0 ? 0.0 : INFINITY);
-            if (rel[b] <= refine->tol) {
-                conv[b] = 1;
-                act[b] = 0;
-            } else if (iters[b] >= refine->max_iter) {
-                act[b] = 0;
-            }
-            n_active += act[b];
+        HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 2, batch), dim3(256), 0, st,
+                                            static_cast<const double2*>(W.R), int64_t(n), mat,
+                                            static_cast<const double2*>(d_X), ldx, stride_x, n, nrhs, W.part,
+                                            static_cast<const int32_t*>(W.active)));
+        HARP_LAUNCH_CHECK();
+        HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                         hipLaunchKernelGGL(refine_check_kernel, dim3(gb), dim3(64), 0, st, W.part, W.znorm, batch,
+                                            refine->tol, refine->max_iter, W.active, rep));
+        HARP_LAUNCH_CHECK();
+        if (it == refine->max_iter) break;
+        if (host && it >= 1) {
+            HARP_HIP_CHECK(hipMemcpyAsync(act_h.data(), W.active, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st));
+            HARP_HIP_CHECK(hipStreamSynchronize(st));
+            n_act = 0;
+            for (int b = 0; b < batch; ++b) n_act += act_h[b] != 0;
+            if (n_act == 0) break;
         }
-        if (n_active == 0) break;
-        HARP_HIP_CHECK(hipMemcpyAsync(W.active, act.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st));
-        // correction: D = LU^-1 R, X += D
+        // correction: D = LU^-1 R, X += D (inactive systems skip every kernel)
         if ((s = solve_into(W.R, n, mat, W.active, true)) != HARP_OK) return s;
-        for (int b = 0; b < batch; ++b) iters[b] += act[b];
-        // make sure the host vectors are not reused before the copies finish
-        HARP_HIP_CHECK(hipStreamSynchronize(st));
     }
+    if (!host) return HARP_OK;
+    std::vector<harp_refine_report> rh(batch);
+    HARP_HIP_CHECK(hipMemcpyAsync(rh.data(), rep, sizeof(harp_refine_report) * batch, hipMemcpyDeviceToHost, st));
+    HARP_HIP_CHECK(hipStreamSynchronize(st));
     bool all = true;
     for (int b = 0; b < batch; ++b) {
-        if (report) {
-            report[b].iters = iters[b];
-            report[b].converged = conv[b];
-            report[b].resid_rel = rel[b];
-        }
-        all = all && conv[b];
+        report[b] = rh[b];
+        all = all && rh[b].converged;
     }
     return all ? HARP_OK : HARP_E_NOCONV;
 }

@@ -13,9 +13,12 @@ struct Rec {
     double flops, bytes;
 };
 
+// Heap objects that are never destroyed: the library has no static object
+// whose destructor runs at process exit (the HIP runtime may already be
+// finalised by then); pooled events are destroyed by harp_prof_release.
 bool g_on = false;
-std::vector<Rec> g_recs;
-std::vector<hipEvent_t> g_pool;
+std::vector<Rec>& g_recs = *new std::vector<Rec>();
+std::vector<hipEvent_t>& g_pool = *new std::vector<hipEvent_t>();
 size_t g_used = 0;
 
 hipEvent_t next_event() {
@@ -77,6 +80,17 @@ extern "C" harp_status harp_prof_enable(int32_t on) {
         prof::g_used = 0;
     }
     return HARP_OK;
+}
+
+extern "C" harp_status harp_prof_release(void) {
+    prof::g_on = false;
+    prof::g_recs.clear();
+    harp_status st = HARP_OK;
+    for (hipEvent_t e : prof::g_pool)
+        if (hipEventDestroy(e) != hipSuccess) st = HARP_E_HIP;
+    prof::g_pool.clear();
+    prof::g_used = 0;
+    return st;
 }
 
 extern "C" harp_status harp_prof_read(int32_t cls, int64_t* launches, double* ms, double* flops, double* bytes) {

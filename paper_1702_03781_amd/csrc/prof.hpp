@@ -33,12 +33,17 @@ void end_ext(int token, double flops, double bytes);
     } while (0)
 
 // Launch kernel<<<grid, block, shmem, stream>>>(args...) with the class's
-// kernel-attached timers (a plain launch when profiling is off).
+// kernel-attached timers; a plain launch when profiling is off (so the
+// launch can be captured in a HIP graph).
 #define HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, kernel, grid, block, shmem, ...)                  \
     do {                                                                                                \
-        hipEvent_t harp_prof_s_ = nullptr, harp_prof_e_ = nullptr;                                      \
-        const int harp_prof_tok_ = ::harp::prof::begin_ext((cls), &harp_prof_s_, &harp_prof_e_);        \
-        hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, harp_prof_s_, harp_prof_e_, 0u,       \
-                              __VA_ARGS__);                                                             \
-        ::harp::prof::end_ext(harp_prof_tok_, (flops), (bytes));                                        \
+        if (!::harp::prof::enabled()) {                                                                 \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                        \
+        } else {                                                                                        \
+            hipEvent_t harp_prof_s_ = nullptr, harp_prof_e_ = nullptr;                                  \
+            const int harp_prof_tok_ = ::harp::prof::begin_ext((cls), &harp_prof_s_, &harp_prof_e_);    \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, harp_prof_s_, harp_prof_e_, 0u,   \
+                                  __VA_ARGS__);                                                         \
+            ::harp::prof::end_ext(harp_prof_tok_, (flops), (bytes));                                    \
+        }                                                                                               \
     } while (0)

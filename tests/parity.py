@@ -4,6 +4,7 @@ comes from the GPU path)."""
 from __future__ import annotations
 
 import functools
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -70,6 +71,31 @@ def oracle_fill_chunked(model, x, y, ri: float = 0.0, chunk: int = 32768) -> np.
     blocks = np.concatenate([ofill.eval_model(model, Rx[i:i + chunk], Ry[i:i + chunk])
                              for i in range(0, Rx.size, chunk)])
     Z[mm[sel], :, nn[sel], :] = blocks
+    for m in range(na):
+        Z[m, :, m, :] = model.Z_self
+    return Z.reshape(na * nm, na * nm)
+
+
+def oracle_fill_threads(model, x, y, ri: float = 0.0, chunk: int = 8192, workers: int = 8) -> np.ndarray:
+    """oracle.fill.fill (the same numbers, entry for entry) with the model
+    evaluated on chunks of pairs by a thread pool (numpy releases the GIL in
+    its array kernels); a thread pool, not processes, because the test
+    process holds a GPU context."""
+    from oracle import fill as ofill
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    na, nm = x.size, model.n_mbf
+    mm, nn = np.meshgrid(np.arange(na), np.arange(na), indexing="ij")
+    sel = mm != nn
+    if ri > 0.0:
+        sel &= np.hypot(x[:, None] - x[None, :], y[:, None] - y[None, :]) <= ri
+    Rx, Ry = (x[:, None] - x[None, :])[sel], (y[:, None] - y[None, :])[sel]
+    Z = np.zeros((na, nm, na, nm), dtype=np.complex128)
+    if Rx.size:
+        with ThreadPoolExecutor(workers) as ex:
+            parts = list(ex.map(lambda i: ofill.eval_model(model, Rx[i:i + chunk], Ry[i:i + chunk]),
+                                range(0, Rx.size, chunk)))
+        Z[mm[sel], :, nn[sel], :] = np.concatenate(parts)
     for m in range(na):
         Z[m, :, m, :] = model.Z_self
     return Z.reshape(na * nm, na * nm)

@@ -7,9 +7,12 @@ at one or two of three frequencies, on one and on two streams -- every system
 against the FP64 oracle (fill per block, X and Y against LAPACK), the padding
 exactly the identity / zero.
 Batched layouts: 48 station layouts of 64..512 elements, 8 of the 16 sweep
-frequencies each (384 systems, n = 528..4056), as timed -- every system by
-recomputed residual, reciprocity and exact padding, and the smallest, a middle
-and the largest system against the oracle."""
+frequencies each (384 systems, n = 528..4056), as timed (one HIP graph over
+four streams) -- every system by recomputed residual, reciprocity and exact
+padding, and every system's fill, X (per port) and Y against the oracle
+(in eight chunks of 48 systems, each its own test).
+Graph replays: the captured step replayed several times, with eager work and
+synchronisations between, equals the eager step bit for bit."""
 import numpy as np
 import pytest
 
@@ -18,7 +21,7 @@ torch = pytest.importorskip("torch")
 from oracle import fill as ofill, fit as ofit, solve as osolve  # noqa: E402
 from workloads import batched_layouts, element, layout_disk  # noqa: E402
 
-from parity import block_eps, oracle_fill_chunked, oracle_models, pack  # noqa: E402
+from parity import block_eps, oracle_fill_threads, oracle_models, pack  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -97,10 +100,13 @@ def test_bad_descriptor_is_reported(api, small):
     y = torch.from_numpy(layouts[0][1]).cuda()
     na = x.numel()
     sys = api.systems_tensor([0, 5, 1, 0], [na, na, na + 1, na], [0, 0, 0, 1], "cuda")
-    _, _, info = api.harp_fill_systems(mb, x, y, sys, na + 1, dtype="c128")
+    _, _, info = api.harp_fill_systems(mb, x, y, sys, na + 1, dtype="c128", check_domain=False)
     torch.cuda.synchronize()
     # model 5 out of range; positions [0, na+1) and [1, na+1) beyond the array
     assert info.cpu().tolist() == [0, -2, -2, -2]
+    with pytest.raises(api.HarpError) as e:
+        api.harp_fill_systems(mb, x, y, sys, na + 1, dtype="c128")
+    assert e.value.status == api.HARP_E_ARG
 
 
 @pytest.fixture(scope="module")
@@ -108,7 +114,7 @@ def batched(api):
     wl, models = oracle_models("station_sweep")
     mb = api.stack_models([pack(api, m) for m in models])
     layouts = batched_layouts()
-    S = api.BatchSolver(mb, layouts, tol=1e-10, streams=2)
+    S = api.BatchSolver(mb, layouts, tol=1e-10, streams=4, graph=True)
     S.step()
     torch.cuda.synchronize()
     return models, layouts, S
@@ -136,27 +142,60 @@ def test_batched_layouts_every_system(api, batched):
         assert not Yp[na:].any() and not Yp[:, na:].any()
 
 
-def test_batched_layouts_sampled_against_oracle(api, batched):
+@pytest.mark.parametrize("chunk", range(8))
+def test_batched_layouts_against_oracle(api, batched, chunk):
+    """Systems [48 chunk, 48 chunk + 48): the oracle's fill of each (its own
+    FP64 Eq. 4 evaluation) against the GPU's block by block, and the GPU's
+    refined X (every port) and Y against LAPACK on the oracle's matrix."""
     models, layouts, S = batched
-    sizes = np.array(S.n_ant)
-    picks = [int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes))]
-    rng = np.random.default_rng(384)
-    for s in picks:
+    worst = 0.0
+    for s in range(48 * chunk, 48 * chunk + 48):
         li, f = S.layout_of[s]
         x, y, _ = layouts[li]
         m = models[f]
-        na = x.size
+        na, n = x.size, x.size * m.n_mbf
         X, Y, _, _ = S.system(s)
-        Zo = oracle_fill_chunked(m, x, y)
-        Zp = S.padded(s)[0].cpu().numpy()
-        eps, zero_ok, _ = block_eps(Zp[:na * m.n_mbf, :na * m.n_mbf], Zo, m.n_mbf)
+        Zo = oracle_fill_threads(m, x, y)
+        Zp = S.padded(s)[0][:n, :n].cpu().numpy()
+        eps, zero_ok, _ = block_eps(Zp, Zo, m.n_mbf)
         assert eps <= 1e-12 and zero_ok, (s, eps)
-        ports = rng.choice(na, min(na, 6), replace=False)
-        Bo = osolve.port_rhs(m.w, na)[:, ports]
-        Xo = np.linalg.solve(Zo, Bo)
-        assert _port_rel(X.cpu().numpy()[:, ports], Xo) <= 1e-6, s
+        for a in range(0, na, max(1, na // 7)):
+            assert np.array_equal(Zp[a * m.n_mbf:(a + 1) * m.n_mbf, a * m.n_mbf:(a + 1) * m.n_mbf], m.Z_self)
+        del Zp
+        Xo = osolve.solve(Zo, osolve.port_rhs(m.w, na))
         Yo = osolve.admittance(Xo, m.w, na)
-        assert _rel(Y.cpu().numpy()[:, ports], Yo) <= 1e-6, s
+        ex, ey = _port_rel(X.cpu().numpy(), Xo), _rel(Y.cpu().numpy(), Yo)
+        assert ex <= 1e-6 and ey <= 1e-6, (s, ex, ey)
+        worst = max(worst, ex, ey)
+    print(f"chunk {chunk}: worst relative error {worst:.2e}")
+
+
+def test_batched_graph_replays_equal_eager(api, small):
+    """The captured step replayed three times, with the program's own eager
+    work and synchronisations between the replays, gives every system's X,
+    Y and report exactly as the eager step (one and two streams)."""
+    models, layouts, mb = small
+    E = api.BatchSolver(mb, layouts, tol=1e-10, max_batch=2)
+    E.step()
+    torch.cuda.synchronize()
+    ref = [(E.system(s)[0].clone(), E.system(s)[1].clone()) for s in range(E.n_systems)]
+    for streams in (1, 2):
+        G = api.BatchSolver(mb, layouts, tol=1e-10, max_batch=2, streams=streams, graph=True)
+        for rep in range(3):
+            for g in G.groups:           # stale values that a replay must overwrite
+                g.X.fill_(float("nan"))
+                g.Y.fill_(float("nan"))
+                g.rep_dev.zero_()
+            torch.cuda.synchronize()
+            G.step()
+            torch.cuda.synchronize()
+            for s in range(G.n_systems):
+                X, Y, info, finfo = G.system(s)
+                assert torch.equal(X, ref[s][0]) and torch.equal(Y, ref[s][1]), (streams, rep, s)
+                assert int(info) == 0 and int(finfo) == 0
+                assert G.reports[s]["converged"] and G.reports[s]["iters"] == E.reports[s]["iters"]
+            # eager work between replays
+            _ = (torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")).sum().item()
 
 
 def test_autotuned_costs(api, small):

@@ -21,11 +21,11 @@ def api():
     return A
 
 
-def _gpu_fill(api, models_o, x, y, dtype, ri=0.0, dual=False):
+def _gpu_fill(api, models_o, x, y, dtype, ri=0.0, dual=False, check_domain=True):
     mb = api.stack_models([pack(api, m) for m in models_o])
     xt = torch.from_numpy(np.asarray(x, np.float64)).cuda()
     yt = torch.from_numpy(np.asarray(y, np.float64)).cuda()
-    Z, Z32, info = api.harp_fill(mb, xt, yt, dtype=dtype, ri=ri, dual=dual)
+    Z, Z32, info = api.harp_fill(mb, xt, yt, dtype=dtype, ri=ri, dual=dual, check_domain=check_domain)
     torch.cuda.synchronize()
     return Z.cpu().numpy(), (Z32.cpu().numpy() if Z32 is not None else None), info.cpu().numpy()
 
@@ -157,8 +157,12 @@ def test_fill_counts_pairs_below_rmin(api):
     y = wl.y.copy()
     x[5] = x[4] + 0.7          # one pair closer than r_min = 1.5 m
     y[5] = y[4]
-    _, _, info = _gpu_fill(api, models, x, y, "c64")
+    _, _, info = _gpu_fill(api, models, x, y, "c64", check_domain=False)
     assert info[0] == ofill.count_below_rmin(models[0], x, y) >= 2
+    # the binding raises it by default
+    with pytest.raises(api.HarpError) as e:
+        _gpu_fill(api, models, x, y, "c64")
+    assert e.value.status == api.HARP_E_DOMAIN
 
 
 def test_fill_rejects_mismatched_model(api):
@@ -167,9 +171,12 @@ def test_fill_rejects_mismatched_model(api):
     mb.n_mbf = 3               # wrong element size for this blob
     xt = torch.from_numpy(wl.x[:10].copy()).cuda()
     yt = torch.from_numpy(wl.y[:10].copy()).cuda()
-    _, _, info = api.harp_fill(mb, xt, yt, dtype="c64")
+    _, _, info = api.harp_fill(mb, xt, yt, dtype="c64", check_domain=False)
     torch.cuda.synchronize()
     assert info.cpu().numpy()[0] == -1
+    with pytest.raises(api.HarpError) as e:
+        api.harp_fill(mb, xt, yt, dtype="c64")
+    assert e.value.status == api.HARP_E_ARG
 
 
 def test_ports_rhs_and_admittance(api):
@@ -188,3 +195,56 @@ def test_ports_rhs_and_admittance(api):
     torch.cuda.synchronize()
     Yo = osolve.admittance(Xo, m.w, wl.n_ant)
     assert np.abs(Y.cpu().numpy()[0] - Yo).max() <= 1e-14 * np.abs(Yo).max()
+
+
+def test_fill_exact_radius_of_influence_and_rmin(api):
+    """Pairs exactly at r = RI and at r = r_min, on axis-aligned offsets whose
+    distance both sides compute exactly (3-4-5 triangles and axis pairs, all
+    coordinates dyadic): a block at r = RI is kept (the inclusive rule), a
+    block one ulp beyond RI is zero, and a pair at exactly r = r_min is inside
+    the model (no domain count)."""
+    wl, models = oracle_models("small16")
+    m = models[0]
+    ri = 5.0
+    # antenna 0 at the origin; 1 at (3, 4): r = 5 = RI exactly; 2 at
+    # (-1.5, 0): r = r_min exactly; 3 at (0, 5 + 2^-48 * 8): just beyond RI
+    x = np.array([0.0, 3.0, -1.5, 0.0, 40.0])
+    y = np.array([0.0, 4.0, 0.0, np.nextafter(5.0, 6.0), 40.0])
+    Z, _, info = _gpu_fill(api, [m], x, y, "c128", ri=ri)
+    assert info[0] == 0
+    Zo = ofill.fill(m, x, y, ri)
+    nm = m.n_mbf
+    blk = lambda M, a, b: M[a * nm:(a + 1) * nm, b * nm:(b + 1) * nm]   # noqa: E731
+    for a, b in [(0, 1), (1, 0), (0, 2), (2, 0)]:
+        assert np.abs(blk(Zo, a, b)).max() > 0
+        assert np.linalg.norm(blk(Z, a, b) - blk(Zo, a, b)) <= 1e-12 * np.linalg.norm(blk(Zo, a, b))
+    for a, b in [(0, 3), (3, 0), (0, 4), (4, 0)]:
+        assert (blk(Z, a, b) == 0).all() and (blk(Zo, a, b) == 0).all()
+    # complex64 evaluation takes the same keep / zero decisions (made in FP64)
+    Z32, _, info32 = _gpu_fill(api, [m], x, y, "c64", ri=ri)
+    assert info32[0] == 0
+    for a, b in [(0, 1), (1, 0), (0, 2), (2, 0)]:
+        assert np.abs(blk(Z32, a, b)).max() > 0
+    for a, b in [(0, 3), (3, 0), (0, 4), (4, 0)]:
+        assert (blk(Z32, a, b) == 0).all()
+
+
+def test_fitted_models_are_reciprocal(api):
+    """The GPU-built model of every frequency of the station sweep gives a
+    complex-symmetric reduced matrix (reciprocity, Z = Z^T) to rounding: the
+    fit's even angular grid makes C^{ST}_p = (-1)^p C^{TS}_p, which the
+    adjoint's solve with Z instead of Z^T relies on."""
+    wl = workload("station_sweep", n_freq=4)
+    s = api.to_device_samples(wl.elem.samples)
+    mb = api.stack_models([api.harp_fit(s, wl.elem.wire_radius, f, P, wl.Q, wl.r_min)
+                           for f, P in zip(wl.freqs, wl.P)])
+    xt = torch.from_numpy(wl.x).cuda()
+    yt = torch.from_numpy(wl.y).cuda()
+    Z, _, _ = api.harp_fill(mb, xt, yt, dtype="c128")
+    for f in range(mb.n_freq):
+        Zf = Z[f]
+        asym = (torch.linalg.norm(Zf - Zf.transpose(0, 1)) / torch.linalg.norm(Zf)).item()
+        assert asym <= 1e-13, (f, asym)
+    # an odd angular grid is refused by the library
+    with pytest.raises(api.HarpError):
+        api.harp_fit(s, wl.elem.wire_radius, wl.freqs[0], wl.P[0], wl.Q, wl.r_min, n_alpha=4 * (wl.P[0] + 1) + 1)

@@ -127,7 +127,7 @@ def test_complex64_pivot_ties_take_the_smallest_row(api):
     A[5, :, 0] = np.nan
     A = A.astype(np.complex64)
     LU = _to_cm(api, A, torch.complex64)
-    F = api.reduced_factor(LU)
+    F = api.reduced_factor(LU, check_singular=False)
     torch.cuda.synchronize()
     piv = F.ipiv.cpu().numpy()
     assert list(piv[:, 0]) == [700, 701, 900, 0, 0, 0], piv[:, 0]
@@ -153,9 +153,38 @@ def test_exact_zero_pivot_sets_info(api):
     A = _rand((2, n, n), 7)
     A[1, :, 37] = 0.0                 # exactly singular: zero column 37
     LU = _to_cm(api, A, torch.complex128)
-    ipiv, info = api.reduced_factor(LU)
+    ipiv, info = api.reduced_factor(LU, check_singular=False)
     torch.cuda.synchronize()
     assert list(info.cpu().numpy()) == [0, 38]
+    # the binding raises it by default
+    with pytest.raises(api.HarpError) as e:
+        api.reduced_factor(_to_cm(api, A, torch.complex128))
+    assert e.value.status == api.HARP_E_SINGULAR
+
+
+def test_station_solver_raises_domain_and_singular(api):
+    """The solver classes read the fill's domain counts and the zero pivots
+    after their step: a pair closer than r_min raises HARP_E_DOMAIN; an
+    element with an all-zero MBF (zero rows and columns in Z) raises
+    HARP_E_SINGULAR."""
+    wl, models = oracle_models("small16")
+    m = models[0]
+    mb = api.stack_models([pack(api, m)])
+    x, y = wl.x.copy(), wl.y.copy()
+    x[5], y[5] = x[4] + 0.7, y[4]
+    S = api.StationSolver(mb, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), "refined")
+    with pytest.raises(api.HarpError) as e:
+        S.step()
+    assert e.value.status == api.HARP_E_DOMAIN
+    C, Zs, w = m.C.copy(), m.Z_self.copy(), m.w.copy()
+    C[1, :], C[:, 1], Zs[1, :], Zs[:, 1] = 0, 0, 0, 0    # MBF 1 interacts with nothing
+    mz = api.pack_model(C, Zs, w, m.samples, m.freq, m.k, 1.0, m.r_min, m.wire_radius)
+    for mode in ("refined", "plain"):
+        S = api.StationSolver(api.stack_models([mz]), torch.from_numpy(wl.x).cuda(),
+                              torch.from_numpy(wl.y).cuda(), mode)
+        with pytest.raises(api.HarpError) as e:
+            S.step()
+        assert e.value.status == api.HARP_E_SINGULAR, mode
 
 
 def test_refinement_report_and_noconv(api):
@@ -173,6 +202,33 @@ def test_refinement_report_and_noconv(api):
     assert rep[0]["iters"] == 0 and not rep[0]["converged"]
     X, rep = api.reduced_solve(F, B, Z64=Z64, tol=1e-12, max_iter=5)
     assert rep[0]["converged"] and 1 <= rep[0]["iters"] <= 5 and rep[0]["resid_rel"] <= 1e-12
+
+
+@pytest.mark.parametrize("max_iter", [0, 1, 4])
+def test_refinement_device_control_matches_host(api, max_iter):
+    """The refinement without a host report (nothing synchronises; every
+    sweep of the budget is enqueued and converged systems skip it) gives the
+    same solution and the same per-system report as with one, bit for bit,
+    over a batch whose systems need different numbers of corrections (one
+    system never converges within the budget)."""
+    n = 130
+    A = _rand((3, n, n), 18) + np.array([3.0, 0.5, 3.0])[:, None, None] * np.sqrt(n) * np.eye(n)[None]
+    Z64 = _to_cm(api, A, torch.complex128)
+    F = api.reduced_factor(_to_cm(api, A.astype(np.complex64), torch.complex64))
+    B = _to_cm(api, _rand((3, n, 5), 19), torch.complex128)
+    tols = 1e-13
+    Xh, rh = api.reduced_solve(F, B, Z64=Z64, tol=tols, max_iter=max_iter, raise_noconv=False)
+    Xd, rd_dev = api.reduced_solve(F, B, Z64=Z64, tol=tols, max_iter=max_iter, device_report=True)
+    torch.cuda.synchronize()
+    rd = api.read_reports(rd_dev)
+    assert rd == rh, (rd, rh)
+    assert torch.equal(Xh, Xd)
+    for r in rh:
+        assert r["iters"] <= max_iter
+    if max_iter >= 4:
+        assert all(r["converged"] for r in rh)
+        ref = np.linalg.solve(A, B.cpu().numpy())
+        assert np.linalg.norm(Xd.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
 def _pipeline(api, models_o, x, y, refined=True):
