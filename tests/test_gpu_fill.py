@@ -211,6 +211,7 @@ def test_fill_exact_radius_of_influence_and_rmin(api):
     x = np.array([0.0, 3.0, -1.5, 0.0, 40.0])
     y = np.array([0.0, 4.0, 0.0, np.nextafter(5.0, 6.0), 40.0])
     Z, _, info = _gpu_fill(api, [m], x, y, "c128", ri=ri)
+    Z = Z[0]
     assert info[0] == 0
     Zo = ofill.fill(m, x, y, ri)
     nm = m.n_mbf
@@ -222,6 +223,7 @@ def test_fill_exact_radius_of_influence_and_rmin(api):
         assert (blk(Z, a, b) == 0).all() and (blk(Zo, a, b) == 0).all()
     # complex64 evaluation takes the same keep / zero decisions (made in FP64)
     Z32, _, info32 = _gpu_fill(api, [m], x, y, "c64", ri=ri)
+    Z32 = Z32[0]
     assert info32[0] == 0
     for a, b in [(0, 1), (1, 0), (0, 2), (2, 0)]:
         assert np.abs(blk(Z32, a, b)).max() > 0
