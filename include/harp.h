@@ -320,6 +320,27 @@ harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dty
                           harp_refine_report *report, void *d_ws, size_t ws_bytes,
                           hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture that must not call hipMalloc, tight serving loops, harnesses that
+ * forbid allocation): reduced_solve without a workspace argument.  Its
+ * scratch (the same layout reduced_solve_ws sizes) lives in a static device
+ * array of reduced_solve_noalloc_max_bytes() bytes (64 MiB) that the library
+ * holds on every GPU it runs on until the process ends; a call whose
+ * reduced_solve_ws size exceeds it returns HARP_E_WORKSPACE and enqueues
+ * nothing.  The call allocates nothing (no hipMalloc / hipFree); the first
+ * call on a device looks up that device's copy of the array (the device of
+ * the caller's stream must be current).  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams, threads or
+ * graphs) race and must be serialised by the caller.  Results, report and
+ * synchronisation behaviour are those of reduced_solve. */
+size_t reduced_solve_noalloc_max_bytes(void);
+harp_status reduced_solve_noalloc(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
+                                  const void *d_LU, int64_t lda, int64_t stride_lu,
+                                  const int32_t *d_ipiv, const void *d_aux, size_t aux_bytes,
+                                  const void *d_B, int64_t ldb, int64_t stride_b, void *d_X,
+                                  int64_t ldx, int64_t stride_x, const harp_refine *refine,
+                                  harp_refine_report *report, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Embedded element patterns (Eqs. 5-6)                                      */
 /* ------------------------------------------------------------------------ */

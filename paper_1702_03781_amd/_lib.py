@@ -68,6 +68,10 @@ SIGNATURES = {
     "reduced_solve": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp, c_i64,
                               c_i64, c_vp, c_i64, c_i64, ctypes.POINTER(HarpRefine),
                               ctypes.POINTER(HarpRefineReport), c_vp, c_sz, c_vp]),
+    "reduced_solve_noalloc_max_bytes": (c_sz, []),
+    "reduced_solve_noalloc": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_sz, c_vp,
+                                      c_i64, c_i64, c_vp, c_i64, c_i64, ctypes.POINTER(HarpRefine),
+                                      ctypes.POINTER(HarpRefineReport), c_vp]),
     "embedded_patterns_ws": (c_i32, [c_i32, c_i32, c_i32, c_szp]),
     "embedded_patterns": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_vp, c_i64, c_i32, c_vp, c_vp,
                                   c_i32, c_vp, c_vp, c_sz, c_vp]),

@@ -31,6 +31,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "cgemm.hpp"
@@ -1538,12 +1539,16 @@ extern "C" harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, 
     return HARP_OK;
 }
 
-extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, const void* d_LU,
-                                     int64_t lda, int64_t stride_lu, const int32_t* d_ipiv, const void* d_aux,
-                                     size_t aux_size, const void* d_B,
-                                     int64_t ldb, int64_t stride_b, void* d_X, int64_t ldx, int64_t stride_x,
-                                     const harp_refine* refine, harp_refine_report* report, void* d_ws,
-                                     size_t ws_bytes, hipStream_t st) {
+namespace harp {
+namespace {
+
+// The solve with its workspace at d_ws (ws_bytes; the caller's, or the
+// library's static scratch).
+harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, const void* d_LU, int64_t lda,
+                       int64_t stride_lu, const int32_t* d_ipiv, const void* d_aux, size_t aux_size,
+                       const void* d_B, int64_t ldb, int64_t stride_b, void* d_X, int64_t ldx, int64_t stride_x,
+                       const harp_refine* refine, harp_refine_report* report, void* d_ws, size_t ws_bytes,
+                       hipStream_t st) {
     if (!d_LU || !d_ipiv || !d_B || !d_X || n <= 0 || nrhs <= 0 || batch <= 0 || batch > 65535) return HARP_E_ARG;
     if (dtype != HARP_C64 && dtype != HARP_C128) return HARP_E_ARG;
     if (!d_aux || aux_size < aux_bytes(n, batch, dtype == HARP_C64 ? 8 : 16)) return HARP_E_WORKSPACE;
@@ -1616,7 +1621,6 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
     // budget is enqueued.
     harp_refine_report* rep = refine->d_report ? static_cast<harp_refine_report*>(refine->d_report) : W.rep;
     const bool host = report != nullptr;
-    std::vector<int32_t> act_h(host ? batch : 0);
     const unsigned gb = unsigned((batch + 63) / 64);
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, batch));
@@ -1658,25 +1662,80 @@ extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, har
         HARP_LAUNCH_CHECK();
         if (it == refine->max_iter) break;
         if (host && it >= 1) {
-            HARP_HIP_CHECK(hipMemcpyAsync(act_h.data(), W.active, sizeof(int32_t) * batch, hipMemcpyDeviceToHost, st));
+            // a system is still active after check `it` exactly when its
+            // iteration count is it + 1 (every check of an active system
+            // counts one correction), so the report alone tells the host
+            HARP_HIP_CHECK(hipMemcpyAsync(report, rep, sizeof(harp_refine_report) * batch, hipMemcpyDeviceToHost,
+                                          st));
             HARP_HIP_CHECK(hipStreamSynchronize(st));
             n_act = 0;
-            for (int b = 0; b < batch; ++b) n_act += act_h[b] != 0;
+            for (int b = 0; b < batch; ++b) n_act += report[b].iters == it + 1;
             if (n_act == 0) break;
         }
         // correction: D = LU^-1 R, X += D (inactive systems skip every kernel)
         if ((s = solve_into(W.R, n, mat, W.active, true)) != HARP_OK) return s;
     }
     if (!host) return HARP_OK;
-    std::vector<harp_refine_report> rh(batch);
-    HARP_HIP_CHECK(hipMemcpyAsync(rh.data(), rep, sizeof(harp_refine_report) * batch, hipMemcpyDeviceToHost, st));
+    HARP_HIP_CHECK(hipMemcpyAsync(report, rep, sizeof(harp_refine_report) * batch, hipMemcpyDeviceToHost, st));
     HARP_HIP_CHECK(hipStreamSynchronize(st));
-    bool all = true;
-    for (int b = 0; b < batch; ++b) {
-        report[b] = rh[b];
-        all = all && rh[b].converged;
+    for (int b = 0; b < batch; ++b)
+        if (!report[b].converged) return HARP_E_NOCONV;
+    return HARP_OK;
+}
+
+// Static scratch of reduced_solve_noalloc: a file-scope device array, one
+// copy per GPU, allocated with the code object and held until the process
+// ends.  Host code never passes `scratch` itself (on the host it is only a
+// stand-in symbol): its device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+harp_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    HARP_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return HARP_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HARP_E_HIP;
+        g_scratch_ptr[dev] = p;
     }
-    return all ? HARP_OK : HARP_E_NOCONV;
+    *out = g_scratch_ptr[dev];
+    return HARP_OK;
+}
+
+}  // namespace
+}  // namespace harp
+
+extern "C" harp_status reduced_solve(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype, const void* d_LU,
+                                     int64_t lda, int64_t stride_lu, const int32_t* d_ipiv, const void* d_aux,
+                                     size_t aux_size, const void* d_B, int64_t ldb, int64_t stride_b, void* d_X,
+                                     int64_t ldx, int64_t stride_x, const harp_refine* refine,
+                                     harp_refine_report* report, void* d_ws, size_t ws_bytes, hipStream_t st) {
+    return solve_core(n, nrhs, batch, dtype, d_LU, lda, stride_lu, d_ipiv, d_aux, aux_size, d_B, ldb, stride_b, d_X,
+                      ldx, stride_x, refine, report, d_ws, ws_bytes, st);
+}
+
+extern "C" size_t reduced_solve_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" harp_status reduced_solve_noalloc(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
+                                             const void* d_LU, int64_t lda, int64_t stride_lu, const int32_t* d_ipiv,
+                                             const void* d_aux, size_t aux_size, const void* d_B, int64_t ldb,
+                                             int64_t stride_b, void* d_X, int64_t ldx, int64_t stride_x,
+                                             const harp_refine* refine, harp_refine_report* report, hipStream_t st) {
+    if (n <= 0 || nrhs <= 0 || batch <= 0 || (dtype != HARP_C64 && dtype != HARP_C128)) return HARP_E_ARG;
+    const size_t need = solve_ws_layout(n, nrhs, batch, dtype, refine != nullptr, nullptr, nullptr);
+    if (need > kScratchBytes) return HARP_E_WORKSPACE;
+    void* ws = nullptr;
+    harp_status s = scratch_for_current_device(&ws);
+    if (s != HARP_OK) return s;
+    return solve_core(n, nrhs, batch, dtype, d_LU, lda, stride_lu, d_ipiv, d_aux, aux_size, d_B, ldb, stride_b, d_X,
+                      ldx, stride_x, refine, report, ws, kScratchBytes, st);
 }
 
 #include "../../include/harp_debug.h"
