@@ -56,6 +56,11 @@ KERNEL_SOURCES = {
 }
 
 
+def _say(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _host():
     cpu_model = None
     try:
@@ -563,6 +568,7 @@ def main():
     y = torch.from_numpy(wl.y).to(dev)
     torch.cuda.synchronize()
 
+    _say("station sweep: models built")
     ref = api.StationSolver(mb, x, y, "refined", tol=args.tol)
     plain = api.StationSolver(mb, x, y, "plain")
 
@@ -588,6 +594,7 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
 
+    _say(f"accuracy vs plain: X {rel_x:.2e}, Y {rel_y:.2e}; timing")
     # timed region (refined path), uninstrumented; an event after every step
     # (recorded on the stream, no synchronisation) gives per-step durations
     for _ in range(args.warmup):
@@ -627,6 +634,7 @@ def main():
     prof = api.prof_read()
     api.prof_enable(False)
 
+    _say(f"refined {ms:.3f} ms per step; kernel timers done")
     ms_plain = None if args.no_plain else timed(plain, max(3, args.steps // 4))
     del plain, Xp, Yp
 
@@ -700,6 +708,7 @@ def main():
     # n = 8192, 1024 ports): a few refined steps on the same launch path
     large = None
     if not args.no_large:
+        _say("large array")
         wl5 = workload("large1024")
         model5 = api.harp_fit(samples, wl5.elem.wire_radius, wl5.freqs[0], wl5.P[0], wl5.Q, wl5.r_min)
         mb5 = api.stack_models([model5])
@@ -724,6 +733,7 @@ def main():
     out["large_array"] = large
 
     if args.cpu_freqs > 0:
+        _say("CPU baseline (oracle)")
         k = min(args.cpu_freqs, nf)
         idx = sorted(set(int(round(i)) for i in np.linspace(0, nf - 1, k)))
         out["cpu_baseline"], acc = cpu_baseline(wl, idx, X_host, Y_host)
