@@ -304,6 +304,10 @@ def bench_batched(args, api, torch, dev):
     # the planner's cost model measured on this GPU (one group per point)
     cost, cost_points = api.autotune_batch_costs(mb)
     S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost, graph=not args.no_graph)
+    # kernel choices (panel width, GEMM tile switch) per group order, timed on this GPU
+    tuning, tuning_points = api.autotune_kernels([(g.n, len(g.members), g.n_ports_pad) for g in S.groups])
+    S.tuning = tuning
+    _say(f"batched: plan of {len(S.groups)} groups, kernel tuning of {len(tuning)} orders")
     S.step()                              # raises on a domain error or a zero pivot
     torch.cuda.synchronize()
     conv = all(r["converged"] for r in S.reports)
@@ -335,7 +339,8 @@ def bench_batched(args, api, torch, dev):
     iters = sorted({r["iters"] for r in S.reports})
 
     # kernel-class timers need eager launches: a timed pass of the eager path
-    E = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost) if not args.no_graph else S
+    E = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost,
+                        tuning=tuning) if not args.no_graph else S
     E.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -397,6 +402,10 @@ def bench_batched(args, api, torch, dev):
             "padded_over_real_entries": padded / entries,
             "plan_cost_model": {"t_group_s": cost[0], "t_order_s": cost[1], "t_system_s": cost[2],
                                 "measured": cost_points},
+            "kernel_tuning": tuning,
+            "kernel_tuning_default_differs": [e for e in tuning if
+                                              (e["panel_width_c64"], e["small_grid_wgs"]) !=
+                                              (api.default_tuning(e["max_order"])["panel_width_c64"], 1024)],
         },
         "reduced_z_entries_per_s_whole_step": entries / (ms * 1e-3),
         "accuracy": {"max_rel_err_X_vs_plain": rel_x, "max_rel_err_Y_vs_plain": rel_y,
@@ -434,6 +443,7 @@ def bench_batched(args, api, torch, dev):
         out["accuracy"]["vs_oracle"] = {"max_rel_err_X_per_port": ex, "max_rel_err_Y": ey,
                                         "ok": ex <= REL_GATE and ey <= REL_GATE}
         out["accuracy"]["ok"] = accuracy_ok and ex <= REL_GATE and ey <= REL_GATE
+    api.set_tuning(None)
     print(json.dumps(out), flush=True)
 
 
@@ -632,11 +642,37 @@ def main():
     torch.cuda.synchronize()
     ms_instr = (time.perf_counter() - t0) * 1e3 / args.steps
     prof = api.prof_read()
+    sites = api.prof_read_sites()
     api.prof_enable(False)
 
     _say(f"refined {ms:.3f} ms per step; kernel timers done")
     ms_plain = None if args.no_plain else timed(plain, max(3, args.steps // 4))
     del plain, Xp, Yp
+
+    # embedded element patterns (Eqs. 5-6) of every port at 110 MHz over the
+    # adjoint configuration's 1024 directions: one dense FP64 product of the
+    # pattern operator (2 x 1024 rows, n columns) with the 256 port solutions
+    from workloads import directions
+    th, ph = directions(1024, seed=304)
+    tht, pht = torch.from_numpy(th).to(dev), torch.from_numpy(ph).to(dev)
+    fi = int(np.argmin(np.abs(wl.freqs - 110e6)))
+    Xf = ref.X[fi]
+    api.embedded_patterns(models[fi], x, y, Xf, tht, pht)
+    torch.cuda.synchronize()
+    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    pe[0].record()
+    for _ in range(reps):
+        api.embedded_patterns(models[fi], x, y, Xf, tht, pht)
+    pe[1].record()
+    torch.cuda.synchronize()
+    ms_pat = pe[0].elapsed_time(pe[1]) / reps
+    pat_flops = 8.0 * (2 * 1024) * na * n
+    patterns = {"workload": "110 MHz, 1024 directions, 256 ports (n = 2048)", "ms": ms_pat,
+                "gemm_flops": pat_flops, "tflops": pat_flops / (ms_pat * 1e-3) / 1e12,
+                "frac_fp64_mfma_whole_call": pat_flops / (ms_pat * 1e-3) / 1e12 / PEAK["fp64_mfma_tflops"],
+                "note": "whole call (MBF radiation vectors, operator build, product) against the product's "
+                        "FP64 matrix-core roof"}
 
     # algorithmic work per step and the method flops of each kernel class
     fill_flops_step = fill_flops_of(wl.P, wl.Q, na * (na - 1), wl.elem.n_mbf)
@@ -694,6 +730,8 @@ def main():
                                    "fill"},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
         "kernel_classes": class_rates(prof, args.steps),
+        "gemm_sites": class_rates(sites, args.steps),
+        "patterns": patterns,
         "roofline": roofline,
         "paper_context": {"fill_s": 10.0, "solve_s": 12.6, "eeps_s": 6.0,
                           "hardware": "Intel Core i7-3770 3.4 GHz (desktop)",

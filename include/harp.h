@@ -249,6 +249,29 @@ harp_status harp_port_admittance(const void *d_models, int64_t model_stride, int
 /* Dense reduced solve (Section I: Gaussian elimination, one RHS per port)   */
 /* ------------------------------------------------------------------------ */
 
+/* Kernel tuning per matrix order (process-wide; set it before enqueueing
+ * work, not while factorisations or solves are being enqueued on other
+ * threads).  An entry applies to orders n <= max_order (entries ascending in
+ * max_order); orders above the last entry, or every order with an empty
+ * table, take the built-in defaults.  panel_width_c64 / _c128: columns per
+ * panel launch of reduced_factor (complex64: 4, 8, or 16 up to order 2048;
+ * complex128: 2, 4, or 8 up to order 2048); small_grid_wgs: GEMM launches of
+ * the factorisation and the solves whose grid has fewer 64 x 64 tiles than
+ * this use 32 x 32 tiles.  harp_set_tuning validates every entry (a width
+ * without a launch configuration for the entry's orders is refused) and
+ * replaces the table; n_entries = 0 restores the defaults (max 64 entries).
+ * harp_default_tuning fills the built-in choice for order n. */
+typedef struct {
+    int32_t max_order;
+    int32_t panel_width_c64;
+    int32_t panel_width_c128;
+    int32_t small_grid_wgs;
+} harp_tuning_entry;
+
+harp_status harp_set_tuning(const harp_tuning_entry *entries, int32_t n_entries);
+harp_status harp_get_tuning(harp_tuning_entry *entries, int32_t capacity, int32_t *n_entries);
+harp_status harp_default_tuning(int32_t n, harp_tuning_entry *entry);
+
 /* Bytes of the factor auxiliary buffer of reduced_factor / reduced_solve. */
 harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t *bytes);
 

@@ -38,6 +38,21 @@ typedef enum {
     HARP_K_COUNT = 8
 } harp_kernel_class;
 
+/* Call sites of the matrix-core GEMM classes (HARP_K_GEMM32 / GEMM64), read
+ * with harp_prof_read_site. */
+typedef enum {
+    HARP_SITE_OTHER = 0,          /* harp_cgemm and the adjoint's products */
+    HARP_SITE_TRAILING = 1,       /* LU trailing update of a super-block */
+    HARP_SITE_CATCH_UP = 2,       /* LU: earlier blocks of the super-block on an outer block's columns */
+    HARP_SITE_DEFERRED_ROWS = 3,  /* LU: the same on an outer block's row block */
+    HARP_SITE_BLOCK_ROW = 4,      /* LU: block row U12 = L11^-1 A12 */
+    HARP_SITE_TRI_INVERSE = 5,    /* inverses of the solve groups' diagonal blocks */
+    HARP_SITE_SOLVE_DIAG = 6,     /* solve: a group's inverse diagonal block */
+    HARP_SITE_SOLVE_UPDATE = 7,   /* solve: update of the rows below / above a group */
+    HARP_SITE_RESIDUAL = 8,       /* refinement residual B - Z X */
+    HARP_SITE_COUNT = 9
+} harp_gemm_site;
+
 /* on != 0: clear the records and start recording; on == 0: stop. */
 harp_status harp_prof_enable(int32_t on);
 
@@ -48,6 +63,10 @@ harp_status harp_prof_release(void);
 
 /* Totals of one class: launches, summed event time (ms), flops, bytes. */
 harp_status harp_prof_read(int32_t cls, int64_t *launches, double *ms, double *flops, double *bytes);
+
+/* The same totals restricted to one call site of a GEMM class. */
+harp_status harp_prof_read_site(int32_t cls, int32_t site, int64_t *launches, double *ms, double *flops,
+                                double *bytes);
 
 #ifdef __cplusplus
 }

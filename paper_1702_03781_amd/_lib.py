@@ -34,6 +34,11 @@ class HarpRefine(ctypes.Structure):
                 ("max_iter", c_i32), ("d_report", c_vp)]
 
 
+class HarpTuningEntry(ctypes.Structure):
+    _fields_ = [("max_order", c_i32), ("panel_width_c64", c_i32), ("panel_width_c128", c_i32),
+                ("small_grid_wgs", c_i32)]
+
+
 class HarpRefineReport(ctypes.Structure):
     _fields_ = [("iters", c_i32), ("converged", c_i32), ("resid_rel", c_dbl)]
 
@@ -61,6 +66,9 @@ SIGNATURES = {
     "harp_port_rhs": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp]),
     "harp_port_admittance": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp,
                                      c_i64, c_i64, c_vp]),
+    "harp_set_tuning": (c_i32, [ctypes.POINTER(HarpTuningEntry), c_i32]),
+    "harp_get_tuning": (c_i32, [ctypes.POINTER(HarpTuningEntry), c_i32, c_i32p]),
+    "harp_default_tuning": (c_i32, [c_i32, ctypes.POINTER(HarpTuningEntry)]),
     "reduced_factor_ws": (c_i32, [c_i32, c_i32, c_i32, c_szp]),
     "reduced_factor": (c_i32, [c_i32, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_sz,
                                c_vp]),
@@ -95,6 +103,8 @@ SIGNATURES = {
 DEBUG_SIGNATURES = {
     "harp_prof_enable": (c_i32, [c_i32]),
     "harp_prof_release": (c_i32, []),
+    "harp_prof_read_site": (c_i32, [c_i32, c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
+                                    ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
     "harp_prof_read": (c_i32, [c_i32, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl),
                                ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl)]),
     "harp_debug_cgemm": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32, c_dbl, c_vp, c_i64, c_i64, c_vp,

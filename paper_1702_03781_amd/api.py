@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from ._lib import HarpElement, HarpError, HarpRefine, HarpRefineReport, check, lib
+from ._lib import HarpElement, HarpError, HarpRefine, HarpRefineReport, HarpTuningEntry, check, lib
 
 C64, C128 = 0, 1
 # status codes of include/harp.h raised by the binding after reading the
@@ -672,7 +672,8 @@ __all__ = [
     "embedded_patterns", "colmajor", "model_bytes", "model_arrays", "read_model_header",
     "to_device_samples", "default_grid", "harp_cgemm", "cmatrix_copy", "harp_port_admittance_vjp",
     "harp_fill_vjp", "embedded_patterns_vjp", "ArrayResponse", "array_response",
-    "save_model", "load_model", "read_reports", "element_hash", "check_flags", "HarpError",
+    "save_model", "load_model", "read_reports", "set_tuning", "get_tuning", "default_tuning",
+    "autotune_kernels", "element_hash", "check_flags", "HarpError",
     "SYSTEM_DTYPE", "systems_tensor", "harp_batch_plan", "autotune_batch_costs", "harp_fill_systems", "harp_port_rhs_systems",
     "harp_port_admittance_systems", "BatchSolver", "StationSolver", "Cell", "harp_tessellate",
     "TessellatedSolver",
@@ -697,8 +698,11 @@ class StationSolver:
     """
 
     def __init__(self, models: ModelBatch, x: torch.Tensor, y: torch.Tensor, mode="refined",
-                 tol: float = 1e-10, max_iter: int = 10, ri: float = 0.0):
+                 tol: float = 1e-10, max_iter: int = 10, ri: float = 0.0, host_report: bool = True):
         self.models, self.mode, self.tol, self.max_iter, self.ri = models, mode, tol, max_iter, float(ri)
+        # host_report=False: the refinement never synchronises (its report stays
+        # on the device; every one of the max_iter sweeps is enqueued)
+        self.host_report = host_report
         dev = models.data.device
         self.x = x.contiguous()
         self.y = y.contiguous()
@@ -724,7 +728,17 @@ class StationSolver:
                                      ctypes.byref(ws_b)), "reduced_solve_ws")
         self.ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=dev)
         self.ws_bytes = ws_b.value
-        self.reports = None
+        self.rep_dev = torch.zeros(nf * 16, dtype=torch.uint8, device=dev)
+        self._reports = None
+
+    @property
+    def reports(self):
+        """Refinement report per frequency (read from the device)."""
+        if self.mode != "refined":
+            return None
+        if self._reports is None:
+            self._reports = _reports_from_device(self.rep_dev)
+        return self._reports
 
     def step(self, events=None, check_flags_: bool = True):
         """One pass of the hot path.  events: optional five torch.cuda.Event
@@ -754,8 +768,9 @@ class StationSolver:
                                _ptr(self.aux), self.aux_bytes, st), "reduced_factor")
         mark(2)
         px, ldx, sx = _cm(self.X, "X")
-        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter)) if refined else None
-        rep = (HarpRefineReport * nf)() if refined else None
+        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter), _ptr(self.rep_dev)) if refined else None
+        rep = (HarpRefineReport * nf)() if (refined and self.host_report) else None
+        self._reports = None
         status = L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.aux),
                                  self.aux_bytes, pb, ldb, sb, px, ldx,
                                  sx, ctypes.byref(ref) if ref is not None else None, rep,
@@ -767,9 +782,6 @@ class StationSolver:
         check(L.harp_port_admittance(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, px, ldx, sx, py,
                                      ldy, sy, st), "harp_port_admittance")
         mark(4)
-        if rep is not None:
-            self.reports = [{"iters": r.iters, "converged": bool(r.converged),
-                             "resid_rel": r.resid_rel} for r in rep]
         if check_flags_:
             fl = self.flags.cpu().numpy()
             check_flags(fl[0], fl[1], "StationSolver.step")
@@ -952,6 +964,89 @@ def autotune_batch_costs(models: ModelBatch, sizes=(96, 256, 480), counts=(1, 8)
     return [float(v) for v in coef / scale], points
 
 
+# --------------------------------------------------------------------------
+# kernel tuning per matrix order
+# --------------------------------------------------------------------------
+
+def set_tuning(entries) -> None:
+    """Install a kernel tuning table (list of dicts with max_order,
+    panel_width_c64, panel_width_c128, small_grid_wgs; ascending max_order);
+    None or [] restores the built-in choices."""
+    entries = entries or []
+    arr = (HarpTuningEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = HarpTuningEntry(int(e["max_order"]), int(e["panel_width_c64"]), int(e["panel_width_c128"]),
+                                 int(e["small_grid_wgs"]))
+    check(lib().harp_set_tuning(arr, len(entries)), "harp_set_tuning")
+
+
+def get_tuning() -> list:
+    arr = (HarpTuningEntry * 64)()
+    n = ctypes.c_int32()
+    check(lib().harp_get_tuning(arr, 64, ctypes.byref(n)), "harp_get_tuning")
+    return [{"max_order": e.max_order, "panel_width_c64": e.panel_width_c64,
+             "panel_width_c128": e.panel_width_c128, "small_grid_wgs": e.small_grid_wgs} for e in arr[:n.value]]
+
+
+def default_tuning(n: int) -> dict:
+    e = HarpTuningEntry()
+    check(lib().harp_default_tuning(int(n), ctypes.byref(e)), "harp_default_tuning")
+    return {"max_order": e.max_order, "panel_width_c64": e.panel_width_c64,
+            "panel_width_c128": e.panel_width_c128, "small_grid_wgs": e.small_grid_wgs}
+
+
+def autotune_kernels(groups, reps: int = 2, seed: int = 11, widths=(16, 8, 4), small_grids=(256, 1024, 4096),
+                     device="cuda"):
+    """Pick, for each (order N, systems c, right-hand sides r) in `groups`,
+    the complex64 panel width and the GEMM small-grid switch that make a
+    complex64 factorisation of c diagonally dominant random systems of order
+    N plus one solve with r right-hand sides fastest on this GPU (each
+    candidate timed over `reps` passes after one warm-up).  Returns (tuning
+    entries for set_tuning / BatchSolver, the measured points).  The table in
+    force when the call started is restored."""
+    saved = get_tuning()
+    rng = np.random.default_rng(seed)
+    entries, points = [], []
+    try:
+        for N, c, r in sorted(set((int(a), int(b), int(d)) for a, b, d in groups)):
+            A = rng.standard_normal((c, N, N)) + 1j * rng.standard_normal((c, N, N))
+            A += 3.0 * math.sqrt(N) * np.eye(N)[None]
+            A0 = colmajor(c, N, N, torch.complex64, device)
+            A0.copy_(torch.from_numpy(A.astype(np.complex64)))
+            B = colmajor(c, N, r, torch.complex128, device)
+            B.copy_(torch.from_numpy(rng.standard_normal((c, N, r)) + 0j))
+            W = colmajor(c, N, N, torch.complex64, device)
+            base = default_tuning(N)
+            best = None
+            for w in widths:
+                for sg in small_grids:
+                    e = dict(base, panel_width_c64=w, small_grid_wgs=sg)
+                    try:
+                        set_tuning([e])
+                    except HarpError:
+                        continue          # no launch configuration for this width at this order
+                    times = []
+                    for it in range(reps + 1):
+                        W.copy_(A0)
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        F = reduced_factor(W, check_singular=False)
+                        reduced_solve(F, B)
+                        torch.cuda.synchronize()
+                        if it:
+                            times.append(time.perf_counter() - t0)
+                    t = min(times)
+                    points.append({"order": N, "systems": c, "rhs": r, "panel_width_c64": w,
+                                   "small_grid_wgs": sg, "seconds": t})
+                    if best is None or t < best[0]:
+                        best = (t, e)
+            entries.append(dict(best[1], max_order=N))
+            del A0, B, W
+    finally:
+        set_tuning(saved)
+    return entries, points
+
+
 class BatchSolver:
     """The refined hot path (FP64 fill written as complex128 and complex64,
     complex64 LU, solve, FP64 refinement, admittances) for a batch of
@@ -960,7 +1055,8 @@ class BatchSolver:
     indices, n_ports): its ports are its first n_ports antennas (default all).
     Systems are grouped by harp_batch_plan and padded per group; groups are
     issued round-robin on `streams` HIP streams (default priority), all
-    buffers allocated once.
+    buffers allocated once.  tuning: kernel tuning entries (autotune_kernels)
+    installed before the work is enqueued.
 
     graph=False: each group's refinement reports to the host (one
     synchronisation per group in the common case).  graph=True: the whole
@@ -970,9 +1066,11 @@ class BatchSolver:
     synchronises inside a step and the reports are read from the device."""
 
     def __init__(self, models: ModelBatch, layouts, tol: float = 1e-10, max_iter: int = 10,
-                 streams: int = 1, ri: float = 0.0, graph: bool = False, sweeps: int = 3, **plan_kw):
+                 streams: int = 1, ri: float = 0.0, graph: bool = False, sweeps: int = 3, tuning=None,
+                 **plan_kw):
         dev = models.data.device
         self.models, self.tol, self.max_iter, self.ri = models, tol, max_iter, ri
+        self.tuning = tuning
         self.graph_mode, self.sweeps = graph, sweeps
         xs, ys, model_idx, n_ant, pos, n_ports, self.layout_of = [], [], [], [], [], [], []
         off = 0
@@ -1049,7 +1147,10 @@ class BatchSolver:
 
     def _enqueue(self, host: bool):
         """Every group's work on the current stream and the side streams
-        (forked from and joined back into the current stream)."""
+        (forked from and joined back into the current stream), under the
+        solver's kernel tuning table (if any)."""
+        if self.tuning is not None:
+            set_tuning(self.tuning)
         main = torch.cuda.current_stream(self.models.data.device)
         sts = [main] + self.streams
         for s in self.streams:
@@ -1201,6 +1302,24 @@ def prof_enable(on: bool) -> None:
 
 
 PROF_CLASSES = ["fill", "getf2", "trsm_lower", "trsm_upper", "gemm_c64", "gemm_c128", "aux", "rank_update"]
+
+
+GEMM_SITES = ["other", "trailing", "catch_up", "deferred_rows", "block_row", "tri_inverse", "solve_diag",
+              "solve_update", "residual"]
+
+
+def prof_read_sites() -> dict:
+    """Per call site of the two GEMM classes: launches, ms, flops, bytes."""
+    out = {}
+    for cls, cname in ((4, "gemm_c64"), (5, "gemm_c128")):
+        for i, site in enumerate(GEMM_SITES):
+            n = ctypes.c_int64()
+            ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            check(lib().harp_prof_read_site(cls, i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                            ctypes.byref(by)), "harp_prof_read_site")
+            if n.value:
+                out[f"{cname}.{site}"] = {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out
 
 
 def prof_read() -> dict:

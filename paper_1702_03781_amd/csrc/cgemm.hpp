@@ -75,13 +75,15 @@ template <typename T> struct GemmArgs {
     // X + outer * sX + i * sX2 (e.g. several blocks of one matrix)
     int inner = 1;
     int64_t sA2 = 0, sB2 = 0, sC2 = 0, sD2 = 0;
+    int site = 0;                // call site tag of the kernel timers (harp_prof.h)
+    int small_grid = 1024;       // grids of fewer 64 x 64 tiles than this take 32 x 32 tiles
 };
 
 template <typename T> struct alignas(16) Vec16 {
     typename Mfma<T>::c_t v[16 / sizeof(typename Mfma<T>::c_t)];
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1, bool PF2 = false>
 __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     using ct = typename Mfma<T>::c_t;
     using acc_t = typename Mfma<T>::acc_t;
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     // global -> registers: A vector e covers rows a_r[e]..+NV-1 of k-row a_k[e];
     // B vector e covers k b_k[e]..+NV-1 of column b_c[e]
     Vec16<T> ra[NA], rb[NBv];
-    auto load_chunk = [&](int k0) {
+    auto load_chunk = [&](int k0, Vec16<T> (&ra)[NA], Vec16<T> (&rb)[NBv]) {
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
             const int v = tid + 256 * e;
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
             }
         }
     };
-    auto store_chunk = [&](int buf) {
+    auto store_chunk = [&](int buf, const Vec16<T> (&ra)[NA], const Vec16<T> (&rb)[NBv]) {
 #pragma unroll
         for (int e = 0; e < NA; ++e) {
             const int v = tid + 256 * e;
@@ -162,12 +164,17 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
         }
     };
 
-    // accumulators start at beta * C; f32 outputs of a lane are four
+    // accumulators: beta * C first (PF2: added after the contraction, so that
+    // the C read does not wait in front of it); f32 outputs of a lane are four
     // consecutive real rows (one 16-byte access when aligned and in range)
     const int b_col = lane & 15;
     const int M2 = 2 * g.M;
     acc_t acc[RB][CB];
-    {
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = acc_t{T(0), T(0), T(0), T(0)};
+    auto add_c = [&]() {
         const T* Cr = g.C ? g.C + 2 * (size_t(bz) * g.sC + size_t(bi) * g.sC2) : nullptr;
         const bool use_c = g.beta != T(0) && Cr != nullptr;
 #pragma unroll
@@ -176,24 +183,24 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
             for (int j = 0; j < CB; ++j) {
                 const int col = col0 + wc + j * 16 + b_col;
                 const int rbase = 2 * (row0 + wr + i * 8);
-                acc[i][j] = acc_t{T(0), T(0), T(0), T(0)};
                 if (!use_c || col >= g.N) continue;
                 const T* cp = Cr + 2 * size_t(col) * g.ldc;
                 if constexpr (sizeof(T) == 4) {
                     const int r4 = rbase + 4 * (lane >> 4);
                     if (VEC && r4 + 4 <= M2) {
                         const f32x4 c4 = *reinterpret_cast<const f32x4*>(cp + r4);
-                        acc[i][j] = c4 * g.beta;
+                        acc[i][j] += c4 * g.beta;
                         continue;
                     }
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int rr = rbase + Mfma<T>::out_row(lane, v);
-                    if (rr < M2) acc[i][j][v] = g.beta * cp[rr];
+                    if (rr < M2) acc[i][j][v] += g.beta * cp[rr];
                 }
             }
-    }
+    };
+    if (!PF2) add_c();
 
     // operand selection for this lane (see the header comment)
     const int s = lane & 1;
@@ -216,15 +223,7 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
         for (int j = 0; j < CB; ++j) bv[j] = reinterpret_cast<const T*>(&Bs[buf][wc + j * 16 + b_col][k])[u];
     };
 
-    const int nchunks = (g.K + BK - 1) / BK;
-    if (nchunks > 0) {
-        load_chunk(0);
-        store_chunk(0);
-    }
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) load_chunk((c + 1) * BK);
+    auto compute = [&](int buf) {
         frag(buf, 0, fa[0], fb[0]);
 #pragma unroll
         for (int st = 0; st < KS; ++st) {
@@ -234,8 +233,42 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
 #pragma unroll
                 for (int j = 0; j < CB; ++j) acc[i][j] = Mfma<T>::op(fa[st & 1][i], fb[st & 1][j], acc[i][j]);
         }
-        if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    };
+    const int nchunks = (g.K + BK - 1) / BK;
+    if constexpr (!PF2) {
+        if (nchunks > 0) {
+            load_chunk(0, ra, rb);
+            store_chunk(0, ra, rb);
+        }
         __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < nchunks) load_chunk((c + 1) * BK, ra, rb);
+            compute(buf);
+            if (c + 1 < nchunks) store_chunk(buf ^ 1, ra, rb);
+            __syncthreads();
+        }
+    } else {
+        // two register sets and two LDS buffers: chunk c is loaded into set
+        // c & 1 two chunks ahead of its use and stored to buffer c & 1 one
+        // chunk ahead (unrolled by two so that every index is a constant)
+        Vec16<T> ra1[NA], rb1[NBv];
+        if (nchunks > 0) load_chunk(0, ra, rb);
+        if (nchunks > 1) load_chunk(BK, ra1, rb1);
+        if (nchunks > 0) store_chunk(0, ra, rb);
+        __syncthreads();
+        for (int c = 0; c < nchunks; c += 2) {
+            if (c + 2 < nchunks) load_chunk((c + 2) * BK, ra, rb);
+            compute(0);
+            if (c + 1 < nchunks) store_chunk(1, ra1, rb1);
+            __syncthreads();
+            if (c + 1 >= nchunks) break;
+            if (c + 3 < nchunks) load_chunk((c + 3) * BK, ra1, rb1);
+            compute(1);
+            if (c + 2 < nchunks) store_chunk(0, ra, rb);
+            __syncthreads();
+        }
+        add_c();
     }
 
     T* Dr = g.D + 2 * (size_t(bz) * g.sD + size_t(bi) * g.sD2);
@@ -273,16 +306,16 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
            ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1, bool PF2 = false>
 inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
-    const int cls = sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64;
+    const int cls = (sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64) | (g.site << 8);
     if (gemm_vec_ok(g))
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC, PF2>), grid,
                              dim3(256), 0, g);
     else
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC, PF2>), grid,
                              dim3(256), 0, g);
 }
 
@@ -290,7 +323,8 @@ inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, do
 // may be zero.  eff_batch (< 0: batch) is the number of outer matrices not
 // skipped by g.active, used only for the work accounting of the profiler.
 // Tile: 64 x 64 (four waves stacked on rows) when that grid has at least
-// four workgroups per CU; smaller grids (the solve's inverse-block products,
+// g.small_grid workgroups (default 1024, four per CU; the LU and solve take it
+// from the tuning table); smaller grids (the solve's inverse-block products,
 // the LU's thin catch-up, deferred-row and in-block products) take 32 x 32
 // tiles for four times the workgroups.  A product in place (D = B) keeps
 // 64-row tiles so that one workgroup reads a whole column block of B before
@@ -309,12 +343,14 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
     const double flops = 8.0 * double(g.M) * double(g.N) * double(g.K) * nb;
     const int64_t wg64 = int64_t((g.M + 63) / 64) * ((g.N + 63) / 64) * batch * g.inner;
     const bool in_place = static_cast<const void*>(g.D) == static_cast<const void*>(g.B);
-    if (!in_place && wg64 < 1024)
+    if (!in_place && wg64 < g.small_grid)
         launch_cgemm<T, 32, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
     else if (sizeof(T) == 8 && g.K >= 1024 && g.N > 32)
         // long FP64 contractions (the refinement residual): 8-wide K chunks at
-        // two workgroups per CU measured ~1.5 % faster than 16-wide at one
-        launch_cgemm<T, 64, 64, 8, 4, 1, 2>(g, batch, stream, flops, bytes);
+        // two workgroups per CU, each chunk fetched two chunks ahead and C
+        // added after the contraction (0.82 of the FP64 peak on the
+        // 2048 x 256 x 2048 residual against 0.74 with one chunk ahead)
+        launch_cgemm<T, 64, 64, 8, 4, 1, 2, true>(g, batch, stream, flops, bytes);
     else if (g.N <= 32 || in_place)
         launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
     else

@@ -1109,16 +1109,58 @@ template <typename T> struct LuCfg {
 // Panel width: the register-resident panel holds RPT x W complex values per
 // thread with 1024 threads (64 VGPRs of budget per lane for the panel); W
 // shrinks as the matrix grows so the panel stays in registers.  Single
-// precision up to 2048 rows: 16 columns as two register blocks of 8.
-template <typename T> inline int panel_width(int n) {
+// precision up to 2048 rows: 16 columns as two register blocks of 8.  These
+// are the defaults of the tuning table (harp_set_tuning), which can choose
+// another feasible width and the GEMM tile switch per order.
+template <typename T> inline int default_panel_width(int n) {
     if (sizeof(T) == 4) return n <= 2048 ? 16 : (n <= 4096 ? 8 : 4);
     return n <= 2048 ? 8 : (n <= 4096 ? 4 : 2);
 }
+
 
 // true when a panel of RPT rows x W complex values per thread fits the VGPR
 // budget of an NT-thread workgroup (512 / (NT / 256) per lane, minus headroom)
 template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
     return RPT * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
+}
+
+// true when a panel of width W has a launch configuration for every height up
+// to n rows (the selection of launch_getf2_w)
+template <typename T, int W> constexpr bool panel_feasible_w(int n) {
+    constexpr int WB = W > 8 ? 8 : W, H = W / WB;
+    if (n <= 1024 * 2) return panel_fits_r<T, 1024, 2, WB * H>();
+    if (H != 1) return false;
+    if (n <= 1024 * 4) return panel_fits_r<T, 1024, 4, WB>();
+    if (n <= 1024 * 8) return panel_fits_r<T, 1024, 8, WB>();
+    return false;
+}
+template <typename T> bool panel_feasible(int W, int n) {
+    switch (W) {
+        case 16: return sizeof(T) == 4 && panel_feasible_w<T, 16>(n);
+        case 8: return panel_feasible_w<T, 8>(n);
+        case 4: return panel_feasible_w<T, 4>(n);
+        case 2: return panel_feasible_w<T, 2>(n);
+    }
+    return false;
+}
+
+// Process-wide tuning table: entries in ascending max_order; an order above
+// the last entry (or an empty table) takes the defaults.
+constexpr int kMaxTuning = 64;
+std::mutex g_tuning_mutex;
+harp_tuning_entry g_tuning[kMaxTuning];
+int g_n_tuning = 0;
+
+struct Tune {
+    int panel_width, small_grid;
+};
+template <typename T> Tune tuning_for(int n) {
+    std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    for (int i = 0; i < g_n_tuning; ++i)
+        if (n <= g_tuning[i].max_order)
+            return Tune{sizeof(T) == 4 ? g_tuning[i].panel_width_c64 : g_tuning[i].panel_width_c128,
+                        g_tuning[i].small_grid_wgs};
+    return Tune{default_panel_width<T>(n), 1024};
 }
 
 // H register blocks of W columns
@@ -1211,7 +1253,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
     // updated once per super-block with a contraction of NS * NB.
     constexpr int NB = LuCfg<T>::NB, NS = LuCfg<T>::NS;
     static_assert(NB <= NBMAX, "outer block");
-    const int W = panel_width<T>(n);
+    const Tune tune = tuning_for<T>(n);
+    const int W = tune.panel_width;
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(zero_i32, dim3((batch + 255) / 256), dim3(256), 0, st, info, batch));
     HARP_LAUNCH_CHECK();
@@ -1224,6 +1267,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
             if (k0 > K0) {
                 GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - k0, nbo, k0 - K0, k0, K0, K0, k0, k0, k0, T(-1), T(1),
                                             nullptr);
+                g.small_grid = tune.small_grid;
+                g.site = HARP_SITE_CATCH_UP;
                 if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
             }
             // row exchanges reach the block row to the right (then the
@@ -1254,6 +1299,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                 if (k0 > K0) {
                     GemmArgs<T> g = sub_gemm<T>(A, lda, sA, nbo, n - kend, k0 - K0, k0, K0, K0, kend, k0, kend,
                                                 T(-1), T(1), nullptr);
+                    g.small_grid = tune.small_grid;
+                    g.site = HARP_SITE_DEFERRED_ROWS;
                     if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
                 }
                 // block row U12 = L11^-1 (exchanged rows), in place: one row
@@ -1278,7 +1325,9 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
                 g.alpha = T(1);
                 g.beta = T(0);
                 g.active = nullptr;
+                g.small_grid = tune.small_grid;
                 static_assert(NBMAX <= 64, "the in-place product needs a single row tile");
+                g.site = HARP_SITE_BLOCK_ROW;
                 if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
             }
         }
@@ -1287,6 +1336,8 @@ harp_status factor_impl(int n, int batch, T* A, int64_t lda, int64_t sA, int32_t
         if (Kend < n) {
             GemmArgs<T> g = sub_gemm<T>(A, lda, sA, n - Kend, n - Kend, Kend - K0, Kend, K0, K0, Kend, Kend, Kend,
                                         T(-1), T(1), nullptr);
+            g.small_grid = tune.small_grid;
+            g.site = HARP_SITE_TRAILING;
             if ((s = cgemm<T>(g, batch, st)) != HARP_OK) return s;
         }
     }
@@ -1310,6 +1361,7 @@ template <typename T>
 harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, const int32_t* ipiv, T* aux,
                         hipStream_t st) {
     const int G = n_groups(n);
+    const int small_grid = tuning_for<T>(n).small_grid;
     harp_status s;
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(group_perm_kernel, dim3(G, batch), dim3(256), 0, st, ipiv, n, G,
@@ -1333,6 +1385,7 @@ harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, 
             const int64_t q11 = 0, q21 = h, q12 = int64_t(h) * kSB, q22 = int64_t(h) * (kSB + 1);
             GemmArgs<T> g1{}, g2{};
             for (GemmArgs<T>* g : {&g1, &g2}) {
+                g->small_grid = small_grid;
                 g->M = h;
                 g->N = h;
                 g->K = h;
@@ -1363,7 +1416,9 @@ harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, 
             g1.sD2 = int64_t(h) * h;
             g2.sA2 = g2.sD2 = int64_t(sz) * (kSB + 1);
             g2.sB2 = int64_t(h) * h;
+            g1.site = HARP_SITE_TRI_INVERSE;
             if ((s = cgemm<T>(g1, batch * G, st)) != HARP_OK) return s;
+            g2.site = HARP_SITE_TRI_INVERSE;
             if ((s = cgemm<T>(g2, batch * G, st)) != HARP_OK) return s;
         }
     }
@@ -1381,8 +1436,9 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     const int64_t sT = int64_t(kSB) * nrhs;
     const int32_t* perm = aux_perm(const_cast<T*>(aux), n, batch);
     const int64_t blk = int64_t(kSB) * kSB;
+    const int small_grid = tuning_for<T>(n).small_grid;
     harp_status s;
-    auto gemm = [&](int M, int N, int K, const T* A, int64_t lda_, int64_t sA_, const T* B, int64_t ldb_,
+    auto gemm = [&](int site, int M, int N, int K, const T* A, int64_t lda_, int64_t sA_, const T* B, int64_t ldb_,
                     int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta) {
         GemmArgs<T> g{};
         g.M = M;
@@ -1403,6 +1459,8 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
         g.alpha = alpha;
         g.beta = beta;
         g.active = active;
+        g.site = site;
+        g.small_grid = small_grid;
         return cgemm<T>(g, batch, st);
     };
     for (int gi = 0; gi < G; ++gi) {
@@ -1413,21 +1471,21 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
                                             perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
         HARP_LAUNCH_CHECK();
         const T* Linv = aux + 2 * (int64_t(gi) * kRec);
-        if ((s = gemm(sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX, T(1), T(0))) !=
+        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX, T(1), T(0))) !=
             HARP_OK)
             return s;
         if (gend < n &&
-            (s = gemm(n - gend, nrhs, sb, LU + 2 * (size_t(g0) * lda + gend), lda, sL, X + 2 * size_t(g0), ldx, sX,
+            (s = gemm(HARP_SITE_SOLVE_UPDATE, n - gend, nrhs, sb, LU + 2 * (size_t(g0) * lda + gend), lda, sL, X + 2 * size_t(g0), ldx, sX,
                       X + 2 * size_t(gend), ldx, sX, T(-1), T(1))) != HARP_OK)
             return s;
     }
     for (int gi = G - 1; gi >= 0; --gi) {
         const int g0 = gi * kSB, sb = std::min(kSB, n - g0);
         const T* Uinv = aux + 2 * (int64_t(gi) * kRec + blk);
-        if ((s = gemm(sb, nrhs, sb, Uinv, kSB, G * kRec, X + 2 * size_t(g0), ldx, sX, Tm, kSB, sT, T(1), T(0))) !=
+        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Uinv, kSB, G * kRec, X + 2 * size_t(g0), ldx, sX, Tm, kSB, sT, T(1), T(0))) !=
             HARP_OK)
             return s;
-        if (g0 > 0 && (s = gemm(g0, nrhs, sb, LU + 2 * (size_t(g0) * lda), lda, sL, Tm, kSB, sT, X, ldx, sX, T(-1),
+        if (g0 > 0 && (s = gemm(HARP_SITE_SOLVE_UPDATE, g0, nrhs, sb, LU + 2 * (size_t(g0) * lda), lda, sL, Tm, kSB, sT, X, ldx, sX, T(-1),
                                 T(1))) != HARP_OK)
             return s;
         // copy the group's solution back
@@ -1505,6 +1563,40 @@ size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveW
 }  // namespace harp
 
 using namespace harp;
+
+extern "C" harp_status harp_set_tuning(const harp_tuning_entry* entries, int32_t n_entries) {
+    if (n_entries < 0 || n_entries > kMaxTuning || (n_entries > 0 && !entries)) return HARP_E_ARG;
+    for (int i = 0; i < n_entries; ++i) {
+        const harp_tuning_entry& e = entries[i];
+        if (e.max_order <= 0 || e.max_order > 8192 || (i > 0 && e.max_order <= entries[i - 1].max_order))
+            return HARP_E_ARG;
+        if (!panel_feasible<float>(e.panel_width_c64, e.max_order) ||
+            !panel_feasible<double>(e.panel_width_c128, e.max_order))
+            return HARP_E_ARG;
+        if (e.small_grid_wgs < 0) return HARP_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    for (int i = 0; i < n_entries; ++i) g_tuning[i] = entries[i];
+    g_n_tuning = n_entries;
+    return HARP_OK;
+}
+
+extern "C" harp_status harp_get_tuning(harp_tuning_entry* entries, int32_t capacity, int32_t* n_entries) {
+    if (!n_entries || capacity < 0 || (capacity > 0 && !entries)) return HARP_E_ARG;
+    std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    *n_entries = g_n_tuning;
+    for (int i = 0; i < g_n_tuning && i < capacity; ++i) entries[i] = g_tuning[i];
+    return HARP_OK;
+}
+
+extern "C" harp_status harp_default_tuning(int32_t n, harp_tuning_entry* entry) {
+    if (!entry || n <= 0 || n > 8192) return HARP_E_ARG;
+    entry->max_order = n;
+    entry->panel_width_c64 = default_panel_width<float>(n);
+    entry->panel_width_c128 = default_panel_width<double>(n);
+    entry->small_grid_wgs = 1024;
+    return HARP_OK;
+}
 
 extern "C" harp_status reduced_factor_ws(int32_t n, int32_t batch, harp_dtype dtype, size_t* bytes) {
     if (!bytes || n <= 0 || batch <= 0 || (dtype != HARP_C64 && dtype != HARP_C128)) return HARP_E_ARG;
@@ -1649,6 +1741,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         g.alpha = -1.0;
         g.beta = 1.0;
         g.active = W.active;
+        g.site = HARP_SITE_RESIDUAL;
         if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                          hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 2, batch), dim3(256), 0, st,

@@ -93,12 +93,14 @@ extern "C" harp_status harp_prof_release(void) {
     return st;
 }
 
-extern "C" harp_status harp_prof_read(int32_t cls, int64_t* launches, double* ms, double* flops, double* bytes) {
+namespace {
+harp_status prof_sum(int32_t cls, int32_t site, int64_t* launches, double* ms, double* flops, double* bytes) {
     if (cls < 0 || cls >= HARP_K_COUNT || !launches || !ms || !flops || !bytes) return HARP_E_ARG;
     int64_t n = 0;
     double t = 0.0, f = 0.0, b = 0.0;
     for (const auto& r : prof::g_recs) {
-        if (r.cls != cls) continue;
+        if ((r.cls & 0xff) != cls) continue;
+        if (site >= 0 && (r.cls >> 8) != site) continue;
         if (hipEventSynchronize(r.stop) != hipSuccess) return HARP_E_HIP;
         float e = 0.0f;
         if (hipEventElapsedTime(&e, r.start, r.stop) != hipSuccess) return HARP_E_HIP;
@@ -112,4 +114,15 @@ extern "C" harp_status harp_prof_read(int32_t cls, int64_t* launches, double* ms
     *flops = f;
     *bytes = b;
     return HARP_OK;
+}
+}  // namespace
+
+extern "C" harp_status harp_prof_read(int32_t cls, int64_t* launches, double* ms, double* flops, double* bytes) {
+    return prof_sum(cls, -1, launches, ms, flops, bytes);
+}
+
+extern "C" harp_status harp_prof_read_site(int32_t cls, int32_t site, int64_t* launches, double* ms, double* flops,
+                                           double* bytes) {
+    if (site < 0 || site >= HARP_SITE_COUNT) return HARP_E_ARG;
+    return prof_sum(cls, site, launches, ms, flops, bytes);
 }

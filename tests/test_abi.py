@@ -94,3 +94,32 @@ def test_new_entry_points_reject_bad_arguments_synchronously(L):
     # ports beyond the padded port count are refused by the kernels' descriptors,
     # a zero port count by the host
     assert L.harp_port_rhs_systems(1, 256, 1, 8, 1, 1, 2, 0, 1, 16, 0, None) == HARP_E_ARG
+
+
+def test_tuning_table_validation(L):
+    """The kernel tuning table: valid entries round-trip, infeasible panel
+    widths and unordered entries are refused, an empty table restores the
+    defaults.  Host only (no device work)."""
+    import ctypes
+
+    from paper_1702_03781_amd._lib import HarpTuningEntry
+
+    def put(rows):
+        arr = (HarpTuningEntry * max(1, len(rows)))(*[HarpTuningEntry(*r) for r in rows])
+        return L.harp_set_tuning(arr, len(rows))
+
+    assert put([(1024, 8, 4, 256), (2048, 16, 8, 1024), (8192, 4, 2, 4096)]) == 0
+    out = (HarpTuningEntry * 8)()
+    n = ctypes.c_int32()
+    assert L.harp_get_tuning(out, 8, ctypes.byref(n)) == 0 and n.value == 3
+    assert [(e.max_order, e.panel_width_c64, e.panel_width_c128, e.small_grid_wgs) for e in out[:3]] == \
+        [(1024, 8, 4, 256), (2048, 16, 8, 1024), (8192, 4, 2, 4096)]
+    assert put([(4096, 16, 4, 1024)]) == -1          # two register blocks need at most 2048 rows
+    assert put([(4096, 8, 8, 1024)]) == -1           # complex128 width 8 has no configuration past 2048 rows
+    assert put([(2048, 8, 4, 1024), (1024, 8, 4, 1024)]) == -1   # not ascending
+    assert put([(2048, 3, 4, 1024)]) == -1
+    assert put([]) == 0
+    assert L.harp_get_tuning(out, 8, ctypes.byref(n)) == 0 and n.value == 0
+    d = HarpTuningEntry()
+    assert L.harp_default_tuning(2048, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (16, 8)
+    assert L.harp_default_tuning(8192, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (4, 2)
