@@ -447,6 +447,68 @@ def bench_batched(args, api, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_large(args, api, torch, dev):
+    """The large array alone: 1024 elements (38 m disk), 8 MBFs, 200 MHz,
+    radius of influence 12 m, n = 8192, 1024 ports; fill, complex64 LU, solve,
+    FP64 refinement and admittances per step; the oracle on one pass."""
+    import numpy as np
+
+    from workloads import workload
+    wl = workload("large1024")
+    samples = api.to_device_samples(wl.elem.samples, dev)
+    model = api.harp_fit(samples, wl.elem.wire_radius, wl.freqs[0], wl.P[0], wl.Q, wl.r_min)
+    mb = api.stack_models([model])
+    S = api.StationSolver(mb, torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev), "refined",
+                          tol=args.tol, ri=wl.ri)
+    S.step()
+    for _ in range(args.warmup):
+        S.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    names = ["fill_and_excitation", "factor", "solve_and_refine", "admittance"]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    S.step(events=ev)
+    torch.cuda.synchronize()
+    ph = {k: ev[i].elapsed_time(ev[i + 1]) for i, k in enumerate(names)}
+    api.prof_enable(True)
+    S.step()
+    torch.cuda.synchronize()
+    prof = api.prof_read()
+    api.prof_enable(False)
+    it = [r["iters"] for r in S.reports]
+    n = wl.n
+    fill_flops = fill_flops_of(wl.P, wl.Q, int(np.count_nonzero(
+        (np.hypot(wl.x[:, None] - wl.x[None, :], wl.y[:, None] - wl.y[None, :]) <= wl.ri))) - wl.n_ant, wl.elem.n_mbf)
+    work = method_flops(n, wl.n_ant, it)
+    mfl = attribute_method_flops(prof, 1, work, fill_flops)
+    for v in prof.values():
+        v["ms_per_step"] = v["ms"]
+    roof = step_roofs(work, fill_flops)
+    out = {
+        "metric": "reduced-Z entries/s + port solves/s at rel err 1e-6 vs FP64 plain path",
+        "value": wl.n_ant / (ms * 1e-3), "unit": "port solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+f64", "data": "synthetic",
+        "config": {"workload": "large array: 1024 elements (38 m disk, 1.5 m min spacing), 8 MBFs x 64 dipole "
+                               "samples, 200 MHz, radius of influence 12 m, n = 8192, 1024 ports; complex64 LU "
+                               "on MFMA + FP64 refinement", "P": wl.P[0], "Q": wl.Q, "refine_tol": args.tol},
+        "reduced_z_entries_per_s": n * n / (prof["fill"]["ms"] * 1e-3) if prof["fill"]["ms"] > 0 else None,
+        "phase_ms": {k: round(v, 3) for k, v in ph.items()}, "refine_iters": it,
+        "kernel_classes": class_rates(prof, 1), "roofline": roofline_from_prof(prof, 1, mfl),
+        "step_roofline": {**{k: round(v, 3) for k, v in roof.items()}, "measured_ms": ms, "frac": roof["ms"] / ms},
+        "cpu_baseline": None,
+    }
+    if args.cpu_freqs > 0:
+        cb, acc = cpu_baseline(wl, [0], S.X.cpu().numpy(), S.Y.cpu().numpy(), min_seconds=0.0, max_passes=1)
+        out["cpu_baseline"] = cb
+        out["accuracy_vs_oracle"] = acc
+    print(json.dumps(out), flush=True)
+
+
 def bench_tessellated(args, api, torch, dev):
     """The 1024-element array (38 m disk, 8 MBFs, 200 MHz) by the overlapping-
     subarray tessellation (every cell's subarray one system of a batch, inner
@@ -510,6 +572,27 @@ def bench_tessellated(args, api, torch, dev):
         "all_converged": conv,
         "cpu_baseline": None,
     }
+    if args.cpu_freqs > 0:
+        # the oracle's tessellated solve of the same array (its own model fit,
+        # every cell's fill and LAPACK solve), and the GPU's ports against it
+        from oracle import fit as ofit
+        from oracle import tessellation as otess
+        mo = ofit.fit(wl.freqs[0], wl.elem.samples, wl.P[0], wl.Q, wl.r_min, wire_radius=wl.elem.wire_radius)
+        t0 = time.perf_counter()
+        per, _ = otess.solve_tessellated(mo, wl.x, wl.y, args.r_in, args.r_ext)
+        dt = time.perf_counter() - t0
+        ex = ey = 0.0
+        for a in range(wl.n_ant):
+            mem, Xg, Yg = T.port(a, 0)
+            mo_mem, Xo, Yo = per[a]
+            ex = max(ex, _rel(Xg.cpu().numpy(), Xo))
+            ey = max(ey, _rel(Yg.cpu().numpy(), Yo))
+        out["cpu_baseline"] = {"value": wl.n_ant / dt, "unit": "port solves/s", "cores": int(_blas_threads()),
+                               "kind": "oracle", "sample": f"the oracle's tessellated solve of the whole array "
+                                                           f"({len(T.cells)} cells, {wl.n_ant} ports), {dt:.1f} s",
+                               "host": _host()}
+        out["accuracy_vs_oracle"] = {"max_rel_err_X_per_port": ex, "max_rel_err_Y_per_port": ey,
+                                     "ok": ex <= REL_GATE and ey <= REL_GATE}
     print(json.dumps(out), flush=True)
 
 
@@ -523,9 +606,10 @@ def main():
                     help="frequencies of the station sweep in the CPU-baseline sample (0: skip every CPU leg)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-large", action="store_true", help="skip the large-array (n = 8192) steps")
-    ap.add_argument("--workload", choices=["station", "batched", "tessellated"], default="station",
+    ap.add_argument("--workload", choices=["station", "batched", "large", "tessellated"], default="station",
                     help="station: the 16-frequency station sweep (default); batched: 48 unequal "
-                         "layouts x 8 frequencies; tessellated: the 1024-element array by overlapping "
+                         "layouts x 8 frequencies; large: the 1024-element array (n = 8192) alone; "
+                         "tessellated: the 1024-element array by overlapping "
                          "subarrays against its full solve")
     ap.add_argument("--r-in", type=float, default=6.0, help="tessellation inner radius (m)")
     ap.add_argument("--r-ext", type=float, default=6.0, help="tessellation extension (m)")
@@ -566,6 +650,8 @@ def main():
         return bench_batched(args, api, torch, dev)
     if args.workload == "tessellated":
         return bench_tessellated(args, api, torch, dev)
+    if args.workload == "large":
+        return bench_large(args, api, torch, dev)
     wl = workload("station_sweep")
     n, na, nf = wl.n, wl.n_ant, len(wl.freqs)
 
