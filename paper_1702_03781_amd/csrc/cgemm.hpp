@@ -83,7 +83,8 @@ template <typename T> struct alignas(16) Vec16 {
     typename Mfma<T>::c_t v[16 / sizeof(typename Mfma<T>::c_t)];
 };
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1, bool PF2 = false>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1, bool PF2 = false,
+          bool XCD = false>
 __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     using ct = typename Mfma<T>::c_t;
     using acc_t = typename Mfma<T>::acc_t;
@@ -99,10 +100,32 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     static_assert(WTM % 8 == 0 && WTN % 16 == 0 && BK % NV == 0 && BK % 2 == 0, "tile shape");
     static_assert(NA >= 1 && NBv >= 1 && NA * NV * 256 == BM * BK && NBv * NV * 256 == BN * BK, "load split");
 
-    const int bz = blockIdx.z / g.inner, bi = blockIdx.z % g.inner;
-    if (g.active && g.active[bz] == 0) return;
+    // workgroup -> (matrix, tile).  With XCD: consecutive workgroups are
+    // dispatched to the eight XCDs in turn, so workgroup L is renumbered so
+    // that XCD k takes the k-th eighth of all tiles in matrix order, and within
+    // a matrix the tiles run in groups of 8 tile rows (column by column inside
+    // a group): the A and B panels a tile reads are then shared by the tiles
+    // resident in the same XCD's L2 instead of being fetched by every XCD.
+    int zz = blockIdx.z, xx = blockIdx.x;
     const int tiles_m = (g.M + BM - 1) / BM;
-    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
+    int tm, tn;
+    if constexpr (XCD) {
+        const long L = long(blockIdx.x) + long(gridDim.x) * blockIdx.z, NT = long(gridDim.x) * gridDim.z;
+        if (NT % 8 == 0) {
+            const long G = (L % 8) * (NT / 8) + L / 8;
+            zz = int(G / gridDim.x);
+            xx = int(G % gridDim.x);
+        }
+        const int tiles_n = (g.N + BN - 1) / BN, GM = 8;
+        const int first = (xx / (GM * tiles_n)) * GM, gm = min(GM, tiles_m - first), r = xx % (GM * tiles_n);
+        tm = first + r % gm;
+        tn = r / gm;
+    } else {
+        tm = xx % tiles_m;
+        tn = xx / tiles_m;
+    }
+    const int bz = zz / g.inner, bi = zz % g.inner;
+    if (g.active && g.active[bz] == 0) return;
     const int row0 = tm * BM, col0 = tn * BN;
 
     const ct* A = reinterpret_cast<const ct*>(g.A) + size_t(bz) * g.sA + size_t(bi) * g.sA2;
@@ -306,16 +329,16 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
            ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1, bool PF2 = false>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1, bool PF2 = false, bool XCD = false>
 inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
     const int cls = (sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64) | (g.site << 8);
     if (gemm_vec_ok(g))
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC, PF2>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC, PF2, XCD>), grid,
                              dim3(256), 0, g);
     else
-        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC, PF2>), grid,
+        HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes, (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC, PF2, XCD>), grid,
                              dim3(256), 0, g);
 }
 
@@ -350,11 +373,11 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
         // two workgroups per CU, each chunk fetched two chunks ahead and C
         // added after the contraction (0.82 of the FP64 peak on the
         // 2048 x 256 x 2048 residual against 0.74 with one chunk ahead)
-        launch_cgemm<T, 64, 64, 8, 4, 1, 2, true>(g, batch, stream, flops, bytes);
+        launch_cgemm<T, 64, 64, 8, 4, 1, 2, true, true>(g, batch, stream, flops, bytes);
     else if (g.N <= 32 || in_place)
         launch_cgemm<T, 64, 32, 16, 4, 1>(g, batch, stream, flops, bytes);
     else
-        launch_cgemm<T, 64, 64, 16, 4, 1>(g, batch, stream, flops, bytes);
+        launch_cgemm<T, 64, 64, 16, 4, 1, 1, false, true>(g, batch, stream, flops, bytes);
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
