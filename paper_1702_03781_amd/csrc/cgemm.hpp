@@ -110,9 +110,10 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     const int tiles_m = (g.M + BM - 1) / BM;
     int tm, tn;
     if constexpr (XCD) {
-        const long L = long(blockIdx.x) + long(gridDim.x) * blockIdx.z, NT = long(gridDim.x) * gridDim.z;
+        // 32-bit arithmetic (the host keeps every grid below 2^31 workgroups)
+        const unsigned L = blockIdx.x + gridDim.x * blockIdx.z, NT = gridDim.x * gridDim.z;
         if (NT % 8 == 0) {
-            const long G = (L % 8) * (NT / 8) + L / 8;
+            const unsigned G = (L % 8) * (NT / 8) + L / 8;
             zz = int(G / gridDim.x);
             xx = int(G % gridDim.x);
         }
@@ -357,6 +358,8 @@ template <typename T>
 inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, int eff_batch = -1) {
     if (g.M <= 0 || g.N <= 0 || batch <= 0 || g.inner <= 0) return HARP_OK;
     if (int64_t(batch) * g.inner > 65535) return HARP_E_ARG;
+    // the kernel numbers workgroups in 32 bits (the 32 x 32 tiling has the most)
+    if (int64_t((g.M + 31) / 32) * ((g.N + 31) / 32) * batch * g.inner >= (int64_t(1) << 31)) return HARP_E_ARG;
     // K == 0 runs the same kernel with an empty contraction: D = beta C
     const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
     // algorithmic bytes: A and B read once, C read when beta != 0, D written

@@ -1028,7 +1028,13 @@ __global__ void __launch_bounds__(256) axpy_kernel(double2* __restrict__ X, int6
 // blockIdx.y selects the matrix (0: M0, 1: M1), so the residual and the
 // solution of a refinement sweep take one launch; matrices whose `active`
 // flag is 0 are skipped.
-constexpr int kNormBlocks = 64;
+constexpr int kNormBlocks = 1024;
+// blocks per matrix: about 16 units (256-row column chunks) per block, at most
+// kNormBlocks, so that one large matrix still spreads over the whole chip
+inline int norm_blocks(int rows, int cols) {
+    const int64_t units = int64_t((rows + 255) / 256) * cols;
+    return int(std::max<int64_t>(1, std::min<int64_t>(kNormBlocks, (units + 15) / 16)));
+}
 __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M0, int64_t ld0, int64_t s0,
                                                             const double2* __restrict__ M1, int64_t ld1, int64_t s1,
                                                             int rows, int cols, double* __restrict__ part,
@@ -1037,28 +1043,49 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __res
     if (active && active[b] == 0) return;
     const double2* M = which ? M1 + size_t(b) * s1 : M0 + size_t(b) * s0;
     const int64_t ld = which ? ld1 : ld0;
-    double acc = 0.0;
+    // four independent accumulators (four loads in flight per thread), added
+    // in a fixed order at the end
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int chunks = (rows + 255) / 256, units = chunks * cols;   // as in convert_kernel
-    for (int u = blockIdx.x; u < units; u += gridDim.x) {
-        const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
-        if (r >= rows) continue;
-        const double2 v = M[int64_t(c) * ld + r];
-        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    const int G = int(gridDim.x);
+    for (int u0 = blockIdx.x; u0 < units; u0 += 4 * G) {
+        double2 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int u = u0 + q * G;
+            const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
+            v[q] = (u < units && r < rows) ? M[int64_t(c) * ld + r] : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = fma(v[q].x, v[q].x, fma(v[q].y, v[q].y, acc[q]));
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    double a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
     __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
     if (threadIdx.x == 0)
-        part[(size_t(b) * 2 + which) * kNormBlocks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        part[(size_t(b) * 2 + which) * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
-// partials of matrix 0 -> Frobenius norm (fixed summation order)
-__global__ void sumsq_final_kernel(const double* __restrict__ part, double* __restrict__ out, int batch) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
-    double s = 0.0;
-    for (int i = 0; i < kNormBlocks; ++i) s += part[size_t(b) * 2 * kNormBlocks + i];
-    out[b] = sqrt(s);
+// Sum of the nblk partials p[0..nblk) by one 256-thread workgroup in a fixed
+// order (strided per thread, then a fixed tree); every thread gets the sum.
+__device__ double block_sum_partials(const double* __restrict__ p, int nblk, double* red) {
+    double a = 0.0;
+    for (int i = int(threadIdx.x); i < nblk; i += 256) a += p[i];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+// partials of matrix 0 -> Frobenius norm; one workgroup per matrix
+__global__ void __launch_bounds__(256) sumsq_final_kernel(const double* __restrict__ part, double* __restrict__ out,
+                                                          int nblk) {
+    const int b = blockIdx.x;
+    __shared__ double red[4];
+    const double sq = block_sum_partials(part + size_t(b) * 2 * kNormBlocks, nblk, red);
+    if (threadIdx.x == 0) out[b] = sqrt(sq);
 }
 
 // Refinement control on the device.  Every system starts active with a
@@ -1074,16 +1101,16 @@ __global__ void refine_init_kernel(int32_t* __restrict__ active, harp_refine_rep
     rep[b].converged = 0;
     rep[b].resid_rel = 0.0;
 }
-__global__ void refine_check_kernel(const double* __restrict__ part, const double* __restrict__ znorm, int batch,
-                                    double tol, int max_iter, int32_t* __restrict__ active,
-                                    harp_refine_report* __restrict__ rep) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch || active[b] == 0) return;
-    double sr = 0.0, sx = 0.0;
-    for (int i = 0; i < kNormBlocks; ++i) {
-        sr += part[size_t(b) * 2 * kNormBlocks + i];
-        sx += part[(size_t(b) * 2 + 1) * kNormBlocks + i];
-    }
+__global__ void __launch_bounds__(256) refine_check_kernel(const double* __restrict__ part, int nblk,
+                                                           const double* __restrict__ znorm, double tol, int max_iter,
+                                                           int32_t* __restrict__ active,
+                                                           harp_refine_report* __restrict__ rep) {
+    const int b = blockIdx.x;
+    if (active[b] == 0) return;   // uniform over the workgroup
+    __shared__ double red[4];
+    const double sr = block_sum_partials(part + size_t(b) * 2 * kNormBlocks, nblk, red);
+    const double sx = block_sum_partials(part + (size_t(b) * 2 + 1) * kNormBlocks, nblk, red);
+    if (threadIdx.x != 0) return;
     const double rn = sqrt(sr), denom = znorm[b] * sqrt(sx);
     const double rel = denom > 0.0 ? rn / denom : (rn == 0.0 ? 0.0 : INFINITY);
     rep[b].resid_rel = rel;
@@ -1517,14 +1544,14 @@ harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t
 // Frobenius norms of `batch` complex128 matrices into out[batch]
 harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, int batch, double* part, double* out,
                       hipStream_t st) {
+    const int nblk = norm_blocks(rows, cols);
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                     hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 1, batch), dim3(256), 0, st,
+                     hipLaunchKernelGGL(sumsq_partial_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
                                         static_cast<const double2*>(M), ld, s, static_cast<const double2*>(nullptr),
                                         int64_t(0), int64_t(0), rows, cols, part, static_cast<const int32_t*>(nullptr)));
     HARP_LAUNCH_CHECK();
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                     hipLaunchKernelGGL(sumsq_final_kernel, dim3((batch + 63) / 64), dim3(64), 0, st, part, out,
-                                        batch));
+                     hipLaunchKernelGGL(sumsq_final_kernel, dim3(batch), dim3(256), 0, st, part, out, nblk));
     HARP_LAUNCH_CHECK();
     return HARP_OK;
 }
@@ -1714,6 +1741,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
     harp_refine_report* rep = refine->d_report ? static_cast<harp_refine_report*>(refine->d_report) : W.rep;
     const bool host = report != nullptr;
     const unsigned gb = unsigned((batch + 63) / 64);
+    const int rnblk = norm_blocks(n, nrhs);   // blocks per matrix of the residual and solution norms
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, batch));
     HARP_LAUNCH_CHECK();
@@ -1744,14 +1772,14 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         g.site = HARP_SITE_RESIDUAL;
         if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kNormBlocks, 2, batch), dim3(256), 0, st,
+                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(rnblk, 2, batch), dim3(256), 0, st,
                                             static_cast<const double2*>(W.R), int64_t(n), mat,
                                             static_cast<const double2*>(d_X), ldx, stride_x, n, nrhs, W.part,
                                             static_cast<const int32_t*>(W.active)));
         HARP_LAUNCH_CHECK();
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(refine_check_kernel, dim3(gb), dim3(64), 0, st, W.part, W.znorm, batch,
-                                            refine->tol, refine->max_iter, W.active, rep));
+                         hipLaunchKernelGGL(refine_check_kernel, dim3(batch), dim3(256), 0, st, W.part, rnblk,
+                                            W.znorm, refine->tol, refine->max_iter, W.active, rep));
         HARP_LAUNCH_CHECK();
         if (it == refine->max_iter) break;
         if (host && it >= 1) {
