@@ -31,6 +31,8 @@
 // on this hardware beats larger tiles for the rank-64 LU updates.
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "prof.hpp"
 
@@ -75,6 +77,10 @@ template <typename T> struct GemmArgs {
     // X + outer * sX + i * sX2 (e.g. several blocks of one matrix)
     int inner = 1;
     int64_t sA2 = 0, sB2 = 0, sC2 = 0, sD2 = 0;
+    // A triangular (1: zero above its diagonal, 2: zero below it): a tile row
+    // contracts only over the K range where its rows of A can be non-zero
+    // (whole zero chunks skipped; the products left out are exact zeros)
+    int tri = 0;
     int site = 0;                // call site tag of the kernel timers (harp_prof.h)
     int small_grid = 1024;       // grids of fewer 64 x 64 tiles than this take 32 x 32 tiles
 };
@@ -97,6 +103,7 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     constexpr int BPAD = NV;                          // keeps B columns 16-byte aligned
     constexpr int KS = BK / 2;                        // MFMA steps per chunk
     static_assert(WM * WN == 4, "four waves");
+    static_assert(BM % BK == 0, "triangular contraction ranges start and end on chunk boundaries");
     static_assert(WTM % 8 == 0 && WTN % 16 == 0 && BK % NV == 0 && BK % 2 == 0, "tile shape");
     static_assert(NA >= 1 && NBv >= 1 && NA * NV * 256 == BM * BK && NBv * NV * 256 == BN * BK, "load split");
 
@@ -258,16 +265,19 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
                 for (int j = 0; j < CB; ++j) acc[i][j] = Mfma<T>::op(fa[st & 1][i], fb[st & 1][j], acc[i][j]);
         }
     };
-    const int nchunks = (g.K + BK - 1) / BK;
+    // contraction range of this tile row (row0 and row0 + BM are multiples of BK)
+    const int kb = g.tri == 2 ? min(g.K, row0) : 0;
+    const int ke = g.tri == 1 ? min(g.K, row0 + BM) : g.K;
+    const int nchunks = (ke - kb + BK - 1) / BK;
     if constexpr (!PF2) {
         if (nchunks > 0) {
-            load_chunk(0, ra, rb);
+            load_chunk(kb, ra, rb);
             store_chunk(0, ra, rb);
         }
         __syncthreads();
         for (int c = 0; c < nchunks; ++c) {
             const int buf = c & 1;
-            if (c + 1 < nchunks) load_chunk((c + 1) * BK, ra, rb);
+            if (c + 1 < nchunks) load_chunk(kb + (c + 1) * BK, ra, rb);
             compute(buf);
             if (c + 1 < nchunks) store_chunk(buf ^ 1, ra, rb);
             __syncthreads();
@@ -277,17 +287,17 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
         // c & 1 two chunks ahead of its use and stored to buffer c & 1 one
         // chunk ahead (unrolled by two so that every index is a constant)
         Vec16<T> ra1[NA], rb1[NBv];
-        if (nchunks > 0) load_chunk(0, ra, rb);
-        if (nchunks > 1) load_chunk(BK, ra1, rb1);
+        if (nchunks > 0) load_chunk(kb, ra, rb);
+        if (nchunks > 1) load_chunk(kb + BK, ra1, rb1);
         if (nchunks > 0) store_chunk(0, ra, rb);
         __syncthreads();
         for (int c = 0; c < nchunks; c += 2) {
-            if (c + 2 < nchunks) load_chunk((c + 2) * BK, ra, rb);
+            if (c + 2 < nchunks) load_chunk(kb + (c + 2) * BK, ra, rb);
             compute(0);
             if (c + 1 < nchunks) store_chunk(1, ra1, rb1);
             __syncthreads();
             if (c + 1 >= nchunks) break;
-            if (c + 3 < nchunks) load_chunk((c + 3) * BK, ra1, rb1);
+            if (c + 3 < nchunks) load_chunk(kb + (c + 3) * BK, ra1, rb1);
             compute(1);
             if (c + 2 < nchunks) store_chunk(0, ra, rb);
             __syncthreads();
@@ -330,8 +340,21 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
            ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
 }
 
+// share of the M x K products a triangular A leaves to BM-row tiles
+inline double tri_share(int tri, int M, int K, int BM) {
+    if (tri == 0 || M <= 0 || K <= 0) return 1.0;
+    double done = 0.0;
+    for (int r0 = 0; r0 < M; r0 += BM) {
+        const int rows = std::min(BM, M - r0);
+        const int kb = tri == 2 ? std::min(K, r0) : 0, ke = tri == 1 ? std::min(K, r0 + BM) : K;
+        done += double(rows) * (ke - kb);
+    }
+    return done / (double(M) * K);
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1, bool PF2 = false, bool XCD = false>
 inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
+    flops *= tri_share(g.tri, g.M, g.K, BM);
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
     const int cls = (sizeof(T) == 4 ? HARP_K_GEMM32 : HARP_K_GEMM64) | (g.site << 8);

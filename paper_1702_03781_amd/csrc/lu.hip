@@ -1446,6 +1446,7 @@ harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, 
             g1.site = HARP_SITE_TRI_INVERSE;
             if ((s = cgemm<T>(g1, batch * G, st)) != HARP_OK) return s;
             g2.site = HARP_SITE_TRI_INVERSE;
+            g2.tri = upper ? 2 : 1;   // A^-1 (upper) or D^-1 (lower): triangular
             if ((s = cgemm<T>(g2, batch * G, st)) != HARP_OK) return s;
         }
     }
@@ -1466,8 +1467,9 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     const int small_grid = tuning_for<T>(n).small_grid;
     harp_status s;
     auto gemm = [&](int site, int M, int N, int K, const T* A, int64_t lda_, int64_t sA_, const T* B, int64_t ldb_,
-                    int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta) {
+                    int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta, int tri = 0) {
         GemmArgs<T> g{};
+        g.tri = tri;
         g.M = M;
         g.N = N;
         g.K = K;
@@ -1498,8 +1500,9 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
                                             perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
         HARP_LAUNCH_CHECK();
         const T* Linv = aux + 2 * (int64_t(gi) * kRec);
-        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX, T(1), T(0))) !=
-            HARP_OK)
+        // the inverse blocks are exactly triangular: their zero halves are skipped
+        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX,
+                      T(1), T(0), 1)) != HARP_OK)
             return s;
         if (gend < n &&
             (s = gemm(HARP_SITE_SOLVE_UPDATE, n - gend, nrhs, sb, LU + 2 * (size_t(g0) * lda + gend), lda, sL, X + 2 * size_t(g0), ldx, sX,
@@ -1509,8 +1512,8 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     for (int gi = G - 1; gi >= 0; --gi) {
         const int g0 = gi * kSB, sb = std::min(kSB, n - g0);
         const T* Uinv = aux + 2 * (int64_t(gi) * kRec + blk);
-        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Uinv, kSB, G * kRec, X + 2 * size_t(g0), ldx, sX, Tm, kSB, sT, T(1), T(0))) !=
-            HARP_OK)
+        if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Uinv, kSB, G * kRec, X + 2 * size_t(g0), ldx, sX, Tm, kSB, sT,
+                      T(1), T(0), 2)) != HARP_OK)
             return s;
         if (g0 > 0 && (s = gemm(HARP_SITE_SOLVE_UPDATE, g0, nrhs, sb, LU + 2 * (size_t(g0) * lda), lda, sL, Tm, kSB, sT, X, ldx, sX, T(-1),
                                 T(1))) != HARP_OK)
