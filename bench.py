@@ -215,10 +215,11 @@ def attribute_method_flops(prof, steps, work, fill_flops_step, refined=True):
     return out
 
 
-def roofline_from_prof(prof, steps, mflops):
+def roofline_from_prof(prof, steps, mflops, fill32=False):
     """Roofline of the kernel class with the largest summed time, from the
     library's dispatch-attached kernel timers, charged with the method's own
-    flops (mflops: per class over the timed steps)."""
+    flops (mflops: per class over the timed steps; fill32: the fill runs in
+    FP32)."""
     cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
                                                     "trsm_lower", "trsm_upper", "rank_update")}
     dom = max(cand, key=lambda k: cand[k]["ms"])
@@ -226,7 +227,8 @@ def roofline_from_prof(prof, steps, mflops):
     launches = max(1, pd["launches"])
     avg_ms = pd["ms"] / launches
     if dom == "fill":
-        bound, peak, unit = "alu", PEAK["fp64_vector_tflops"], "TFLOP/s"
+        bound, unit = "alu", "TFLOP/s"
+        peak = PEAK["fp32_vector_tflops"] if fill32 else PEAK["fp64_vector_tflops"]
         achieved = mflops["fill"] / (pd["ms"] * 1e-3) / 1e12
     elif dom in ("gemm_c64", "gemm_c128"):
         bound = "mfma"
@@ -268,14 +270,16 @@ def roofline_from_prof(prof, steps, mflops):
     }
 
 
-def step_roofs(work, fill_flops, refined=True):
+def step_roofs(work, fill_flops, refined=True, fill32=False):
     """Time of one step if every part ran at its roof: FP32 matrix cores for
     the complex64 LU and solves (FP64 for the plain path), FP64 matrix cores
-    for the residuals, FP64 vector units for the fill."""
+    for the residuals, FP64 vector units for the fill (FP32 vector units for
+    the complex64 fill)."""
     lu_peak = PEAK["fp32_mfma_tflops"] if refined else PEAK["fp64_mfma_tflops"]
     t_lu = (work["lu"] + work["solves"]) / (lu_peak * 1e12)
     t_res = work["residuals"] / (PEAK["fp64_mfma_tflops"] * 1e12)
-    t_fill = fill_flops / (PEAK["fp64_vector_tflops"] * 1e12)
+    fill_peak = PEAK["fp32_vector_tflops"] if fill32 else PEAK["fp64_vector_tflops"]
+    t_fill = fill_flops / (fill_peak * 1e12)
     return {"ms": 1e3 * (t_lu + t_res + t_fill), "lu_and_solves_ms": 1e3 * t_lu,
             "residuals_ms": 1e3 * t_res, "fill_ms": 1e3 * t_fill}
 
@@ -458,8 +462,8 @@ def bench_large(args, api, torch, dev):
     samples = api.to_device_samples(wl.elem.samples, dev)
     model = api.harp_fit(samples, wl.elem.wire_radius, wl.freqs[0], wl.P[0], wl.Q, wl.r_min)
     mb = api.stack_models([model])
-    S = api.StationSolver(mb, torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev), "refined",
-                          tol=args.tol, ri=wl.ri)
+    S = api.StationSolver(mb, torch.from_numpy(wl.x).to(dev), torch.from_numpy(wl.y).to(dev),
+                          "refined32" if args.fill == "c64" else "refined", tol=args.tol, ri=wl.ri)
     S.step()
     for _ in range(args.warmup):
         S.step()
@@ -487,7 +491,8 @@ def bench_large(args, api, torch, dev):
     mfl = attribute_method_flops(prof, 1, work, fill_flops)
     for v in prof.values():
         v["ms_per_step"] = v["ms"]
-    roof = step_roofs(work, fill_flops)
+    f32 = args.fill == "c64"
+    roof = step_roofs(work, fill_flops, fill32=f32)
     out = {
         "metric": "reduced-Z entries/s + port solves/s at rel err 1e-6 vs FP64 plain path",
         "value": wl.n_ant / (ms * 1e-3), "unit": "port solves/s", "n_gpus": 1, "steps": args.steps,
@@ -495,10 +500,11 @@ def bench_large(args, api, torch, dev):
         "dtype": "c64+f64", "data": "synthetic",
         "config": {"workload": "large array: 1024 elements (38 m disk, 1.5 m min spacing), 8 MBFs x 64 dipole "
                                "samples, 200 MHz, radius of influence 12 m, n = 8192, 1024 ports; complex64 LU "
-                               "on MFMA + FP64 refinement", "P": wl.P[0], "Q": wl.Q, "refine_tol": args.tol},
+                               "on MFMA + FP64 refinement, " + ("complex64 fill" if f32 else "FP64 fill"),
+                   "P": wl.P[0], "Q": wl.Q, "refine_tol": args.tol, "fill": args.fill},
         "reduced_z_entries_per_s": n * n / (prof["fill"]["ms"] * 1e-3) if prof["fill"]["ms"] > 0 else None,
         "phase_ms": {k: round(v, 3) for k, v in ph.items()}, "refine_iters": it,
-        "kernel_classes": class_rates(prof, 1), "roofline": roofline_from_prof(prof, 1, mfl),
+        "kernel_classes": class_rates(prof, 1), "roofline": roofline_from_prof(prof, 1, mfl, fill32=f32),
         "step_roofline": {**{k: round(v, 3) for k, v in roof.items()}, "measured_ms": ms, "frac": roof["ms"] / ms},
         "cpu_baseline": None,
     }
@@ -605,6 +611,10 @@ def main():
     ap.add_argument("--cpu-freqs", type=int, default=16,
                     help="frequencies of the station sweep in the CPU-baseline sample (0: skip every CPU leg)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--fill", choices=["c64", "c128"], default="c64",
+                    help="station sweep: precision of the timed fill and of the residual's matrix (c64: "
+                         "complex64 fill, FP64 residual against it; c128: FP64 fill); the other is timed "
+                         "beside it")
     ap.add_argument("--no-large", action="store_true", help="skip the large-array (n = 8192) steps")
     ap.add_argument("--workload", choices=["station", "batched", "large", "tessellated"], default="station",
                     help="station: the 16-frequency station sweep (default); batched: 48 unequal "
@@ -665,7 +675,10 @@ def main():
     torch.cuda.synchronize()
 
     _say("station sweep: models built")
-    ref = api.StationSolver(mb, x, y, "refined", tol=args.tol)
+    mode = "refined32" if args.fill == "c64" else "refined"
+    alt_mode = "refined" if mode == "refined32" else "refined32"
+    fill32 = mode == "refined32"
+    ref = api.StationSolver(mb, x, y, mode, tol=args.tol)
     plain = api.StationSolver(mb, x, y, "plain")
 
     # accuracy gate: refined path vs the plain FP64 GPU path (the oracle
@@ -733,7 +746,23 @@ def main():
 
     _say(f"refined {ms:.3f} ms per step; kernel timers done")
     ms_plain = None if args.no_plain else timed(plain, max(3, args.steps // 4))
-    del plain, Xp, Yp
+    # the other precision of the fill and residual matrix, for comparison
+    alt = api.StationSolver(mb, x, y, alt_mode, tol=args.tol)
+    Xa, Ya = alt.step()
+    torch.cuda.synchronize()
+    da = (Xa - Xp).abs().pow(2).sum(dim=(1, 2)).sqrt() / Xp.abs().pow(2).sum(dim=(1, 2)).sqrt()
+    dya = (Ya - Yp).abs().pow(2).sum(dim=(1, 2)).sqrt() / Yp.abs().pow(2).sum(dim=(1, 2)).sqrt()
+    ms_alt = timed(alt, max(3, args.steps // 2))
+    ev_alt = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    alt.step(events=ev_alt)
+    torch.cuda.synchronize()
+    alt_block = {"mode": ("complex64 fill, FP64 residual against the complex64 matrix" if alt_mode == "refined32"
+                          else "FP64 fill (complex128 residual matrix plus its complex64 rounding)"),
+                 "ms_per_step": ms_alt, "port_solves_per_s": nf * na / (ms_alt * 1e-3),
+                 "fill_and_excitation_ms": ev_alt[0].elapsed_time(ev_alt[1]),
+                 "max_rel_err_X_vs_plain": float(da.max()), "max_rel_err_Y_vs_plain": float(dya.max())}
+    del alt, Xa, Ya, plain, Xp, Yp
+    torch.cuda.empty_cache()
 
     # embedded element patterns (Eqs. 5-6) of every port at 110 MHz over the
     # adjoint configuration's 1024 directions: one dense FP64 product of the
@@ -762,12 +791,14 @@ def main():
 
     # algorithmic work per step and the method flops of each kernel class
     fill_flops_step = fill_flops_of(wl.P, wl.Q, na * (na - 1), wl.elem.n_mbf)
+
+
     work = method_flops(n, na, iters, refined=True)
     mfl = attribute_method_flops(prof, args.steps, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
-    roofline = roofline_from_prof(prof, args.steps, mfl)
-    roof_ref = step_roofs(work, fill_flops_step, refined=True)
+    roofline = roofline_from_prof(prof, args.steps, mfl, fill32=fill32)
+    roof_ref = step_roofs(work, fill_flops_step, refined=True, fill32=fill32)
     work_plain = method_flops(n, na, [0] * nf, refined=False)
     roof_plain = step_roofs(work_plain, fill_flops_step, refined=False)
     t_fill = prof["fill"]["ms_per_step"] * 1e-3
@@ -794,9 +825,11 @@ def main():
         "config": {
             "workload": ("station sweep: 256 elements (19 m disk, 1.5 m min spacing), 8 MBFs x 64 "
                          "dipole samples, 16 frequencies 50-350 MHz, n = 2048, 256 ports each; "
-                         "complex64 LU on MFMA + FP64 refinement"),
+                         + ("complex64 fill (FP32 evaluation, FP64 phase argument), complex64 LU on MFMA, "
+                            "FP64 refinement against the complex64 matrix" if fill32 else
+                            "FP64 fill, complex64 LU on MFMA, FP64 refinement against the complex128 matrix")),
             "n_ant": na, "n_mbf": wl.elem.n_mbf, "n_freq": nf, "n": n, "rhs_per_freq": na,
-            "P": list(wl.P), "Q": wl.Q, "refine_tol": args.tol,
+            "P": list(wl.P), "Q": wl.Q, "refine_tol": args.tol, "fill": args.fill,
         },
         # entries/s over the fill's own time (the fill kernel's timers); the
         # port solves over the factorisation and solve phases
@@ -812,12 +845,13 @@ def main():
             "step_at_roofs_ms": roof_plain["ms"], "step_roof_frac": roof_plain["ms"] / ms_plain},
         "step_roofline": {**{k: round(v, 4) for k, v in roof_ref.items()}, "measured_ms": ms,
                           "frac": roof_ref["ms"] / ms,
-                          "parts": "FP32 matrix cores: LU + solves; FP64 matrix cores: residuals; FP64 vector: "
-                                   "fill"},
+                          "parts": ("FP32 matrix cores: LU + solves; FP64 matrix cores: residuals; "
+                                    + ("FP32 vector: fill" if fill32 else "FP64 vector: fill"))},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
         "kernel_classes": class_rates(prof, args.steps),
         "gemm_sites": class_rates(sites, args.steps),
         "patterns": patterns,
+        "other_fill_precision": alt_block,
         "roofline": roofline,
         "paper_context": {"fill_s": 10.0, "solve_s": 12.6, "eeps_s": 6.0,
                           "hardware": "Intel Core i7-3770 3.4 GHz (desktop)",
@@ -836,7 +870,7 @@ def main():
         wl5 = workload("large1024")
         model5 = api.harp_fit(samples, wl5.elem.wire_radius, wl5.freqs[0], wl5.P[0], wl5.Q, wl5.r_min)
         mb5 = api.stack_models([model5])
-        S5 = api.StationSolver(mb5, torch.from_numpy(wl5.x).to(dev), torch.from_numpy(wl5.y).to(dev), "refined",
+        S5 = api.StationSolver(mb5, torch.from_numpy(wl5.x).to(dev), torch.from_numpy(wl5.y).to(dev), mode,
                                tol=args.tol, ri=wl5.ri)
         ms5 = timed(S5, 3)
         ev5 = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -846,11 +880,12 @@ def main():
         it5 = [r["iters"] for r in S5.reports]
         n5 = wl5.n
         large = {"workload": "large array: 1024 elements (38 m disk), 8 MBFs x 64 samples, 200 MHz, radius of "
-                             "influence 12 m, n = 8192, 1024 ports; complex64 LU + FP64 refinement",
+                             "influence 12 m, n = 8192, 1024 ports; complex64 LU + FP64 refinement, "
+                             + ("complex64 fill" if fill32 else "FP64 fill"),
                  "steps": 3, "ms_per_step": ms5, "port_solves_per_s": wl5.n_ant / (ms5 * 1e-3),
                  "reduced_z_entries_per_s": n5 * n5 / (ph5["fill_and_excitation"] * 1e-3),
                  "phase_ms": {k: round(v, 3) for k, v in ph5.items()}, "refine_iters": it5,
-                 "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5), 0.0)["ms"]}
+                 "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5), 0.0, fill32=fill32)["ms"]}
         X5, Y5 = S5.X[0].cpu().numpy(), S5.Y[0].cpu().numpy()
         del S5
         torch.cuda.empty_cache()

@@ -123,8 +123,11 @@ harp_status harp_fit(const harp_element *elem, double freq_hz, int32_t P, int32_
  *   dtype HARP_C128: FP64 evaluation, d_Z complex128.
  *   dtype HARP_C64 : FP32 evaluation (distance and k r reduced in FP64),
  *                    d_Z complex64.
- *   d_Z32 != NULL (only with HARP_C128): the FP64 result is also written
- *                    rounded to complex64 into d_Z32 (ld32, stride32).
+ *   d_Z32 != NULL: a second complex64 copy in d_Z32 (ld32, stride32): with
+ *                    HARP_C128 the FP64 result rounded to complex64, with
+ *                    HARP_C64 the same complex64 values as d_Z (so that one
+ *                    copy can be factored in place while the other stays
+ *                    the matrix a refinement residual is taken against).
  * d_info[f] (int32, device) receives the number of ordered pairs with
  * r < r_min (outside the model; their blocks hold the polynomial continued
  * beyond t = 1), or -1 if model f does not match n_mbf / Q / p_max.
@@ -298,12 +301,16 @@ harp_status reduced_factor(int32_t n, int32_t batch, harp_dtype dtype, void *d_A
  * complex128).  d_report (optional, device, [batch] harp_refine_report,
  * caller-owned) receives the per-system report on the device. */
 typedef struct {
-    const void *d_Z;     /* complex128 matrices the residual is taken against */
+    const void *d_Z;     /* matrices the residual is taken against (see z_complex64) */
     int64_t ldz;
     int64_t stride_z;
     double tol;          /* stop when ||B - Z X||_F <= tol ||Z||_F ||X||_F */
     int32_t max_iter;    /* maximum number of correction sweeps (>= 0) */
     void *d_report;      /* optional device copy of the report (NULL: none) */
+    int32_t z_complex64; /* 0: d_Z is complex128; 1: d_Z is complex64, each
+                            entry widened to FP64 as the residual reads it
+                            (the refinement then converges to the solution
+                            of that complex64 matrix) */
 } harp_refine;
 
 typedef struct {

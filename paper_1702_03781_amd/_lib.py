@@ -31,7 +31,7 @@ class HarpElement(ctypes.Structure):
 
 class HarpRefine(ctypes.Structure):
     _fields_ = [("d_Z", c_vp), ("ldz", c_i64), ("stride_z", c_i64), ("tol", c_dbl),
-                ("max_iter", c_i32), ("d_report", c_vp)]
+                ("max_iter", c_i32), ("d_report", c_vp), ("z_complex64", c_i32)]
 
 
 class HarpTuningEntry(ctypes.Structure):

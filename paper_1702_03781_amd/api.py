@@ -342,7 +342,8 @@ def harp_fill(models: ModelBatch, x: torch.Tensor, y: torch.Tensor, dtype="c64",
               Z: torch.Tensor | None = None, Z32: torch.Tensor | None = None,
               dual: bool = False, check_domain: bool = True):
     """Fill the reduced matrices of all frequencies (Eq. 4).  Returns (Z, Z32,
-    info); Z32 is the complex64 copy when dual=True (dtype must be c128).
+    info); with dual=True, Z32 is a second complex64 copy (dtype c128: the
+    FP64 result rounded; dtype c64: the same values as Z).
     With check_domain (default) the call waits for the fill and raises
     HARP_E_DOMAIN if a pair is closer than the model's r_min (HARP_E_ARG for a
     model that does not match); otherwise info holds the counts."""
@@ -432,7 +433,9 @@ def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
                   Z64: torch.Tensor | None = None, tol: float = 1e-12, max_iter: int = 10,
                   raise_noconv: bool = True, device_report: bool = False):
     """Solve with the factors of reduced_factor; optional FP64 refinement
-    against Z64.  Returns (X, reports or None).  device_report=True: the
+    against Z64 (complex128, or complex64 widened to FP64 in the residual:
+    the refinement then converges to that complex64 matrix's solution).
+    Returns (X, reports or None).  device_report=True: the
     refinement runs without any host synchronisation (all max_iter sweeps
     enqueued, converged systems skipping them) and the second value is the
     device array of reports (read it with read_reports after the stream)."""
@@ -454,7 +457,10 @@ def reduced_solve(F: Factors, B: torch.Tensor, X: torch.Tensor | None = None,
         pz, ldz, sz = _cm(Z64, "Z64")
         if device_report:
             rep_dev = torch.zeros(b * 16, dtype=torch.uint8, device=LU.device)
-        ref = HarpRefine(pz, ldz, sz, float(tol), int(max_iter), _ptr(rep_dev))
+        if Z64.dtype not in (torch.complex128, torch.complex64):
+            raise HarpError(HARP_E_ARG, "reduced_solve: Z64 must be complex128 or complex64")
+        ref = HarpRefine(pz, ldz, sz, float(tol), int(max_iter), _ptr(rep_dev),
+                         int(Z64.dtype == torch.complex64))
         rep = None if device_report else (HarpRefineReport * b)()
     ws_b = ctypes.c_size_t()
     check(lib().reduced_solve_ws(n, nrhs, b, dt, int(ref is not None), ctypes.byref(ws_b)),
@@ -692,6 +698,10 @@ class StationSolver:
     its complex64 rounding (factored on the matrix cores), complex64 solve,
     FP64 iterative refinement to `tol` (convergence decided on the device;
     the host waits once, after the first correction, in the common case).
+    mode "refined32": complex64 fill (FP32 evaluation, FP64 phase argument)
+    written twice, one copy factored on the matrix cores and the other kept
+    as the matrix of the FP64 residual (widened as it is read); the
+    refinement converges to the complex64 matrix's solution.
     mode "plain": complex128 fill, factor and solve (the FP64 reference path).
     ri > 0: radius of influence of the fill (blocks of pairs farther apart are
     zero, Section II-D).
@@ -709,8 +719,13 @@ class StationSolver:
         self.n_ant = int(x.numel())
         n = self.n = self.n_ant * models.n_mbf
         nf = models.n_freq
-        self.Z64 = colmajor(nf, n, n, torch.complex128, dev)
-        self.Z32 = colmajor(nf, n, n, torch.complex64, dev) if mode == "refined" else None
+        if mode not in ("refined", "refined32", "plain"):
+            raise ValueError(f"StationSolver: unknown mode {mode!r}")
+        self.refined = mode != "plain"
+        # the matrix of the residual (refined modes) or the factored one (plain)
+        self.Z64 = colmajor(nf, n, n, torch.complex128, dev) if mode != "refined32" else None
+        self.Zr = colmajor(nf, n, n, torch.complex64, dev) if mode == "refined32" else None
+        self.Z32 = colmajor(nf, n, n, torch.complex64, dev) if self.refined else None
         self.B = colmajor(nf, n, self.n_ant, torch.complex128, dev)
         self.X = colmajor(nf, n, self.n_ant, torch.complex128, dev)
         self.Y = colmajor(nf, self.n_ant, self.n_ant, torch.complex128, dev)
@@ -718,13 +733,13 @@ class StationSolver:
         self.flags = torch.zeros((2, nf), dtype=torch.int32, device=dev)
         self.info, self.finfo = self.flags[0], self.flags[1]
         self.ipiv = torch.empty((nf, n), dtype=torch.int32, device=dev)
-        dt = C64 if mode == "refined" else C128
+        dt = C64 if self.refined else C128
         aux_b = ctypes.c_size_t()
         check(lib().reduced_factor_ws(n, nf, dt, ctypes.byref(aux_b)), "reduced_factor_ws")
         self.aux = torch.empty(max(1, aux_b.value), dtype=torch.uint8, device=dev)
         self.aux_bytes = aux_b.value
         ws_b = ctypes.c_size_t()
-        check(lib().reduced_solve_ws(n, self.n_ant, nf, dt, int(mode == "refined"),
+        check(lib().reduced_solve_ws(n, self.n_ant, nf, dt, int(self.refined),
                                      ctypes.byref(ws_b)), "reduced_solve_ws")
         self.ws = torch.empty(max(1, ws_b.value), dtype=torch.uint8, device=dev)
         self.ws_bytes = ws_b.value
@@ -734,7 +749,7 @@ class StationSolver:
     @property
     def reports(self):
         """Refinement report per frequency (read from the device)."""
-        if self.mode != "refined":
+        if not self.refined:
             return None
         if self._reports is None:
             self._reports = _reports_from_device(self.rep_dev)
@@ -750,13 +765,14 @@ class StationSolver:
         L = lib()
         mb, n, na, nf = self.models, self.n, self.n_ant, self.models.n_freq
         st = _stream(mb.data.device)
-        refined = self.mode == "refined"
+        refined = self.refined
+        z32 = self.mode == "refined32"
         mark = (lambda i: events[i].record()) if events is not None else (lambda i: None)
         mark(0)
-        pz, ldz, sz = _cm(self.Z64, "Z64")
+        pz, ldz, sz = _cm(self.Zr, "Zr") if z32 else _cm(self.Z64, "Z64")
         p32, ld32, s32 = _cm(self.Z32, "Z32") if refined else (0, 0, 0)
         check(L.harp_fill(_ptr(mb.data), mb.stride, nf, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
-                          _ptr(self.y), na, self.ri, C128, pz, ldz, sz, p32, ld32, s32,
+                          _ptr(self.y), na, self.ri, C64 if z32 else C128, pz, ldz, sz, p32, ld32, s32,
                           _ptr(self.info), st), "harp_fill")
         pb, ldb, sb = _cm(self.B, "B")
         check(L.harp_port_rhs(_ptr(mb.data), mb.stride, nf, mb.n_mbf, na, pb, ldb, sb, st),
@@ -768,7 +784,8 @@ class StationSolver:
                                _ptr(self.aux), self.aux_bytes, st), "reduced_factor")
         mark(2)
         px, ldx, sx = _cm(self.X, "X")
-        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter), _ptr(self.rep_dev)) if refined else None
+        ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter), _ptr(self.rep_dev),
+                         int(z32)) if refined else None
         rep = (HarpRefineReport * nf)() if (refined and self.host_report) else None
         self._reports = None
         status = L.reduced_solve(n, na, nf, dt, pf, ldf, sf, _ptr(self.ipiv), _ptr(self.aux),

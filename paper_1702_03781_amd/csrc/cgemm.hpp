@@ -83,6 +83,9 @@ template <typename T> struct GemmArgs {
     int tri = 0;
     int site = 0;                // call site tag of the kernel timers (harp_prof.h)
     int small_grid = 1024;       // grids of fewer 64 x 64 tiles than this take 32 x 32 tiles
+    // T = double only: A held as complex64 (A must be null), each entry
+    // widened to FP64 as it is loaded; lda and sA count complex64 elements
+    const float* A32 = nullptr;
 };
 
 template <typename T> struct alignas(16) Vec16 {
@@ -90,8 +93,10 @@ template <typename T> struct alignas(16) Vec16 {
 };
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool VEC, int OCC = 1, bool PF2 = false,
-          bool XCD = false>
+          bool XCD = false, bool A32 = false>
 __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
+    static_assert(!A32 || sizeof(T) == 8, "a complex64 A operand is widened for FP64 products only");
+    static_assert(!A32 || (BM * BK) % 512 == 0, "complex64 A: whole 16-byte pairs of rows per thread");
     using ct = typename Mfma<T>::c_t;
     using acc_t = typename Mfma<T>::acc_t;
     constexpr int NV = int(16 / sizeof(ct));          // complex per 16-byte access
@@ -136,7 +141,9 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     if (g.active && g.active[bz] == 0) return;
     const int row0 = tm * BM, col0 = tn * BN;
 
-    const ct* A = reinterpret_cast<const ct*>(g.A) + size_t(bz) * g.sA + size_t(bi) * g.sA2;
+    const size_t a_off = size_t(bz) * g.sA + size_t(bi) * g.sA2;
+    const ct* A = A32 ? nullptr : reinterpret_cast<const ct*>(g.A) + a_off;
+    const float2* Aw = A32 ? reinterpret_cast<const float2*>(g.A32) + a_off : nullptr;
     const ct* B = reinterpret_cast<const ct*>(g.B) + size_t(bz) * g.sB + size_t(bi) * g.sB2;
 
     __shared__ __attribute__((aligned(16))) ct As[2][BK][BM + APAD];
@@ -156,13 +163,37 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
             const int v = tid + 256 * e;
             const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
             const int gk = k0 + kk, gr = row0 + r;
-            const ct* src = A + size_t(gk) * g.lda + gr;
-            if (VEC && gk < g.K && gr + NV <= g.M) {
-                ra[e] = *reinterpret_cast<const Vec16<T>*>(src);
-            } else {
+            if constexpr (!A32) {
+                const ct* src = A + size_t(gk) * g.lda + gr;
+                if (VEC && gk < g.K && gr + NV <= g.M) {
+                    ra[e] = *reinterpret_cast<const Vec16<T>*>(src);
+                } else {
 #pragma unroll
-                for (int q = 0; q < NV; ++q)
-                    ra[e].v[q] = (gk < g.K && gr + q < g.M) ? src[q] : ct{T(0), T(0)};
+                    for (int q = 0; q < NV; ++q)
+                        ra[e].v[q] = (gk < g.K && gr + q < g.M) ? src[q] : ct{T(0), T(0)};
+                }
+            }
+        }
+        if constexpr (A32) {
+            // complex64 A: one 16-byte access holds two consecutive rows; the
+            // raw bytes wait in register slot 2 e2 and are widened only when
+            // stored (after the current chunk's products), so that the load
+            // stays in flight during them
+#pragma unroll
+            for (int e2 = 0; e2 < NA / 2; ++e2) {
+                const int v = tid + 256 * e2;
+                const int kk = v / (BM / 2), r = (v % (BM / 2)) * 2;
+                const int gk = k0 + kk, gr = row0 + r;
+                const float2* src = Aw + size_t(gk) * g.lda + gr;
+                float4 q;
+                if (VEC && gk < g.K && gr + 2 <= g.M) {
+                    q = *reinterpret_cast<const float4*>(src);
+                } else {
+                    const float2 w0 = (gk < g.K && gr < g.M) ? src[0] : float2{0.f, 0.f};
+                    const float2 w1 = (gk < g.K && gr + 1 < g.M) ? src[1] : float2{0.f, 0.f};
+                    q = float4{w0.x, w0.y, w1.x, w1.y};
+                }
+                __builtin_memcpy(&ra[2 * e2], &q, sizeof(q));
             }
         }
 #pragma unroll
@@ -181,11 +212,23 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
         }
     };
     auto store_chunk = [&](int buf, const Vec16<T> (&ra)[NA], const Vec16<T> (&rb)[NBv]) {
+        if constexpr (A32) {
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            const int v = tid + 256 * e;
-            const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
-            *reinterpret_cast<Vec16<T>*>(&As[buf][kk][r]) = ra[e];
+            for (int e2 = 0; e2 < NA / 2; ++e2) {
+                const int v = tid + 256 * e2;
+                const int kk = v / (BM / 2), r = (v % (BM / 2)) * 2;
+                float4 q;
+                __builtin_memcpy(&q, &ra[2 * e2], sizeof(q));
+                As[buf][kk][r] = ct{T(q.x), T(q.y)};
+                As[buf][kk][r + 1] = ct{T(q.z), T(q.w)};
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NA; ++e) {
+                const int v = tid + 256 * e;
+                const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
+                *reinterpret_cast<Vec16<T>*>(&As[buf][kk][r]) = ra[e];
+            }
         }
 #pragma unroll
         for (int e = 0; e < NBv; ++e) {
@@ -336,8 +379,11 @@ template <typename T> inline bool gemm_vec_ok(const GemmArgs<T>& g) {
     constexpr int64_t NV = 16 / (2 * sizeof(T));
     auto al = [](const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
     auto ev = [](int64_t x) { return x % NV == 0; };
-    return al(g.A) && al(g.B) && al(g.C) && al(g.D) && ev(g.lda) && ev(g.ldb) && ev(g.ldc) && ev(g.ldd) &&
-           ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) && ev(g.sD2);
+    // a complex64 A (FP64 products) is read two rows per 16-byte access
+    auto ev2 = [&](int64_t x) { return g.A32 == nullptr || x % 2 == 0; };
+    return al(g.A) && al(g.A32) && al(g.B) && al(g.C) && al(g.D) && ev(g.lda) && ev(g.ldb) && ev(g.ldc) &&
+           ev(g.ldd) && ev(g.sA) && ev(g.sB) && ev(g.sC) && ev(g.sD) && ev(g.sA2) && ev(g.sB2) && ev(g.sC2) &&
+           ev(g.sD2) && ev2(g.lda) && ev2(g.sA) && ev2(g.sA2);
 }
 
 // share of the M x K products a triangular A leaves to BM-row tiles
@@ -354,6 +400,23 @@ inline double tri_share(int tri, int M, int K, int BM) {
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, int OCC = 1, bool PF2 = false, bool XCD = false>
 inline void launch_cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, double flops, double bytes) {
+    if constexpr (sizeof(T) == 8) {
+        if (g.A32) {
+            flops *= tri_share(g.tri, g.M, g.K, BM);
+            const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+            const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
+            const int cls = HARP_K_GEMM64 | (g.site << 8);
+            if (gemm_vec_ok(g))
+                HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes,
+                                     (cgemm_kernel<T, BM, BN, BK, WM, WN, true, OCC, PF2, XCD, true>), grid,
+                                     dim3(256), 0, g);
+            else
+                HARP_PROF_EXT_LAUNCH(cls, stream, flops, bytes,
+                                     (cgemm_kernel<T, BM, BN, BK, WM, WN, false, OCC, PF2, XCD, true>), grid,
+                                     dim3(256), 0, g);
+            return;
+        }
+    }
     flops *= tri_share(g.tri, g.M, g.K, BM);
     const int tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
     const dim3 grid(unsigned(tiles), 1u, unsigned(batch * g.inner));
@@ -386,9 +449,11 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
     // K == 0 runs the same kernel with an empty contraction: D = beta C
     const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
     // algorithmic bytes: A and B read once, C read when beta != 0, D written
+    if (g.A32 && (sizeof(T) != 8 || g.A)) return HARP_E_ARG;
     const bool reads_c = g.beta != T(0) && g.C != nullptr;
-    const double bytes = 2.0 * sizeof(T) * nb *
-                         (double(g.M) * g.K + double(g.K) * g.N + double(g.M) * g.N * (reads_c ? 2.0 : 1.0));
+    const double a_bytes = g.A32 ? 8.0 : 2.0 * sizeof(T);
+    const double bytes = nb * (a_bytes * double(g.M) * g.K +
+                               2.0 * sizeof(T) * (double(g.K) * g.N + double(g.M) * g.N * (reads_c ? 2.0 : 1.0)));
     const double flops = 8.0 * double(g.M) * double(g.N) * double(g.K) * nb;
     const int64_t wg64 = int64_t((g.M + 63) / 64) * ((g.N + 63) / 64) * batch * g.inner;
     const bool in_place = static_cast<const void*>(g.D) == static_cast<const void*>(g.B);

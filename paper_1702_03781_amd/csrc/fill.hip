@@ -301,7 +301,7 @@ harp_status launch_fill_q(const FillArgs& a, dim3 grid, hipStream_t stream) {
     case QQ:                                                                               \
         HARP_PROF_EXT_LAUNCH(HARP_K_FILL, stream, 0.0,                                     \
                              double(a.n_freq) * double(a.n_ant) * a.n_mbf * double(a.n_ant) * \
-                                 a.n_mbf * (DUAL ? 24.0 : double(2 * sizeof(R))),          \
+                                 a.n_mbf * (double(2 * sizeof(R)) + (DUAL ? 8.0 : 0.0)),   \
                              (fill_kernel<R, QQ, DUAL>), grid, dim3(256), lds, a, a.models, \
                              a.x, a.y, a.Z, a.Z32);                                        \
         break;
@@ -331,7 +331,6 @@ harp_status fill_launch(FillArgs& a, harp_dtype dtype, hipStream_t stream) {
     if (a.ldz < n || (a.n_freq > 1 && a.stride_z < a.ldz * n)) return HARP_E_ARG;
     if (a.model_stride < 256 || (a.model_stride % 256) != 0) return HARP_E_ARG;
     if (a.Z32) {
-        if (dtype != HARP_C128) return HARP_E_ARG;
         if (a.ld32 < n || (a.n_freq > 1 && a.stride32 < a.ld32 * n)) return HARP_E_ARG;
     }
     if (fill_lds_bytes(a, dtype == HARP_C64 ? 4 : 8) > size_t(kMaxCoefLds)) return HARP_E_ARG;
@@ -342,7 +341,8 @@ harp_status fill_launch(FillArgs& a, harp_dtype dtype, hipStream_t stream) {
     const int ppw = fill_ppw(a.n_mbf);
     const int tiles = ((a.n_ant + ppw - 1) / ppw) * ((a.n_ant + kTileN - 1) / kTileN);
     const dim3 grid{unsigned(tiles), unsigned(a.n_freq), 1u};
-    if (dtype == HARP_C64) return launch_fill_q<float, false>(a, grid, stream);
+    if (dtype == HARP_C64)
+        return a.Z32 ? launch_fill_q<float, true>(a, grid, stream) : launch_fill_q<float, false>(a, grid, stream);
     if (a.Z32) return launch_fill_q<double, true>(a, grid, stream);
     return launch_fill_q<double, false>(a, grid, stream);
 }

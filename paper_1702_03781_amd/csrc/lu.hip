@@ -1035,13 +1035,17 @@ inline int norm_blocks(int rows, int cols) {
     const int64_t units = int64_t((rows + 255) / 256) * cols;
     return int(std::max<int64_t>(1, std::min<int64_t>(kNormBlocks, (units + 15) / 16)));
 }
-__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M0, int64_t ld0, int64_t s0,
+// V0: element type of M0 (double2, or float2 for a complex64 matrix; the
+// squares are accumulated in FP64 either way); M1 is complex128
+template <typename V0>
+__global__ void __launch_bounds__(256) sumsq_partial_kernel(const V0* __restrict__ M0, int64_t ld0, int64_t s0,
                                                             const double2* __restrict__ M1, int64_t ld1, int64_t s1,
                                                             int rows, int cols, double* __restrict__ part,
                                                             const int32_t* __restrict__ active) {
     const int b = blockIdx.z, which = blockIdx.y;
     if (active && active[b] == 0) return;
-    const double2* M = which ? M1 + size_t(b) * s1 : M0 + size_t(b) * s0;
+    const V0* Ma = which ? nullptr : M0 + size_t(b) * s0;
+    const double2* Mb = which ? M1 + size_t(b) * s1 : nullptr;
     const int64_t ld = which ? ld1 : ld0;
     // four independent accumulators (four loads in flight per thread), added
     // in a fixed order at the end
@@ -1054,7 +1058,15 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __res
         for (int q = 0; q < 4; ++q) {
             const int u = u0 + q * G;
             const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
-            v[q] = (u < units && r < rows) ? M[int64_t(c) * ld + r] : double2{0.0, 0.0};
+            v[q] = double2{0.0, 0.0};
+            if (u < units && r < rows) {
+                if (which) {
+                    v[q] = Mb[int64_t(c) * ld + r];
+                } else {
+                    const V0 e = Ma[int64_t(c) * ld + r];
+                    v[q] = double2{double(e.x), double(e.y)};
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = fma(v[q].x, v[q].x, fma(v[q].y, v[q].y, acc[q]));
@@ -1545,13 +1557,22 @@ harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t
 }
 
 // Frobenius norms of `batch` complex128 matrices into out[batch]
-harp_status fro_norms(const void* M, int64_t ld, int64_t s, int rows, int cols, int batch, double* part, double* out,
-                      hipStream_t st) {
+// (complex64: M holds complex64 values, squared in FP64)
+harp_status fro_norms(const void* M, bool complex64, int64_t ld, int64_t s, int rows, int cols, int batch,
+                      double* part, double* out, hipStream_t st) {
     const int nblk = norm_blocks(rows, cols);
-    HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                     hipLaunchKernelGGL(sumsq_partial_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
-                                        static_cast<const double2*>(M), ld, s, static_cast<const double2*>(nullptr),
-                                        int64_t(0), int64_t(0), rows, cols, part, static_cast<const int32_t*>(nullptr)));
+    if (complex64)
+        HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                         hipLaunchKernelGGL(sumsq_partial_kernel<float2>, dim3(nblk, 1, batch), dim3(256), 0, st,
+                                            static_cast<const float2*>(M), ld, s,
+                                            static_cast<const double2*>(nullptr), int64_t(0), int64_t(0), rows,
+                                            cols, part, static_cast<const int32_t*>(nullptr)));
+    else
+        HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                         hipLaunchKernelGGL(sumsq_partial_kernel<double2>, dim3(nblk, 1, batch), dim3(256), 0, st,
+                                            static_cast<const double2*>(M), ld, s,
+                                            static_cast<const double2*>(nullptr), int64_t(0), int64_t(0), rows,
+                                            cols, part, static_cast<const int32_t*>(nullptr)));
     HARP_LAUNCH_CHECK();
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(sumsq_final_kernel, dim3(batch), dim3(256), 0, st, part, out, nblk));
@@ -1679,6 +1700,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
     const bool ref = refine != nullptr;
     if (ref) {
         if (!refine->d_Z || refine->ldz < n || refine->max_iter < 0 || !(refine->tol >= 0.0)) return HARP_E_ARG;
+        if (refine->z_complex64 != 0 && refine->z_complex64 != 1) return HARP_E_ARG;
         if (batch > 1 && refine->stride_z < refine->ldz * n) return HARP_E_ARG;
     }
     const size_t need = solve_ws_layout(n, nrhs, batch, dtype, ref, nullptr, nullptr);
@@ -1748,7 +1770,9 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                      hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, batch));
     HARP_LAUNCH_CHECK();
-    if ((s = fro_norms(refine->d_Z, refine->ldz, refine->stride_z, n, n, batch, W.part, W.znorm, st)) != HARP_OK)
+    const bool z32 = refine->z_complex64 != 0;
+    if ((s = fro_norms(refine->d_Z, z32, refine->ldz, refine->stride_z, n, n, batch, W.part, W.znorm, st)) !=
+        HARP_OK)
         return s;
     int n_act = batch;   // systems the host knows to be active (work accounting of the timers only)
     for (int it = 0;; ++it) {
@@ -1757,7 +1781,9 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         g.M = n;
         g.N = nrhs;
         g.K = n;
-        g.A = static_cast<const double*>(refine->d_Z);
+        // complex64 Z: widened to FP64 as the residual product loads it
+        g.A = z32 ? nullptr : static_cast<const double*>(refine->d_Z);
+        g.A32 = z32 ? static_cast<const float*>(refine->d_Z) : nullptr;
         g.lda = refine->ldz;
         g.sA = refine->stride_z;
         g.B = static_cast<const double*>(d_X);
@@ -1775,7 +1801,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         g.site = HARP_SITE_RESIDUAL;
         if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(rnblk, 2, batch), dim3(256), 0, st,
+                         hipLaunchKernelGGL(sumsq_partial_kernel<double2>, dim3(rnblk, 2, batch), dim3(256), 0, st,
                                             static_cast<const double2*>(W.R), int64_t(n), mat,
                                             static_cast<const double2*>(d_X), ldx, stride_x, n, nrhs, W.part,
                                             static_cast<const int32_t*>(W.active)));

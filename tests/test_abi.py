@@ -96,6 +96,19 @@ def test_new_entry_points_reject_bad_arguments_synchronously(L):
     assert L.harp_port_rhs_systems(1, 256, 1, 8, 1, 1, 2, 0, 1, 16, 0, None) == HARP_E_ARG
 
 
+def test_refinement_matrix_precision_flag_is_checked(L):
+    """harp_refine.z_complex64 must be 0 (complex128 Z) or 1 (complex64 Z,
+    widened in the residual); anything else is refused before the workspace
+    check and before any launch (placeholder pointers)."""
+    from paper_1702_03781_amd._lib import HarpRefine
+    HARP_E_ARG, HARP_E_WORKSPACE = -1, -6
+    for flag, want in ((2, HARP_E_ARG), (-1, HARP_E_ARG), (1, HARP_E_WORKSPACE), (0, HARP_E_WORKSPACE)):
+        ref = HarpRefine(1, 16, 256, 1e-10, 3, None, flag)
+        st = L.reduced_solve(16, 1, 1, 0, 1, 16, 256, 1, 1, 1 << 30, 1, 16, 16, 1, 16, 16,
+                             ctypes.byref(ref), None, None, 0, None)
+        assert st == want, (flag, st)
+
+
 def test_tuning_table_validation(L):
     """The kernel tuning table: valid entries round-trip, infeasible panel
     widths and unordered entries are refused, an empty table restores the

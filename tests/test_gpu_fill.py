@@ -66,12 +66,14 @@ def test_fill_small16(api, dtype):
     assert sym <= (1e-13 if dtype == "c128" else 1e-6)
 
 
-@pytest.mark.parametrize("mode", ["c64", "c128", "dual"])
+@pytest.mark.parametrize("mode", ["c64", "c128", "dual", "twin64"])
 def test_fill_station_sweep_all_frequencies(api, mode):
-    """Full station sweep (256 elements, 8 MBFs, 16 frequencies), every block."""
+    """Full station sweep (256 elements, 8 MBFs, 16 frequencies), every block.
+    dual: complex128 plus its complex64 rounding; twin64: the complex64 fill
+    written twice."""
     wl, models = oracle_models("station_sweep")
-    dtype = "c64" if mode == "c64" else "c128"
-    Zg, Z32, info = _gpu_fill(api, models, wl.x, wl.y, dtype, dual=(mode == "dual"))
+    dtype = "c64" if mode in ("c64", "twin64") else "c128"
+    Zg, Z32, info = _gpu_fill(api, models, wl.x, wl.y, dtype, dual=mode in ("dual", "twin64"))
     assert (info == 0).all()
     for f, m in enumerate(models):
         Zo = ofill.fill(m, wl.x, wl.y)
@@ -80,6 +82,9 @@ def test_fill_station_sweep_all_frequencies(api, mode):
         if mode == "dual":
             # the complex64 copy is the rounding of the FP64 result
             assert np.array_equal(Z32[f], Zg[f].astype(np.complex64))
+        if mode == "twin64":
+            # the second copy holds the same complex64 values
+            assert Z32.dtype == np.complex64 and np.array_equal(Z32[f], Zg[f])
 
 
 def test_fill_ragged_and_radius_of_influence(api):

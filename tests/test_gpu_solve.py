@@ -231,13 +231,23 @@ def test_refinement_device_control_matches_host(api, max_iter):
         assert np.linalg.norm(Xd.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-def _pipeline(api, models_o, x, y, refined=True):
+def _pipeline(api, models_o, x, y, refined=True, keep_z=False):
+    """refined: True (FP64 fill, complex64 LU, FP64 refinement against the
+    complex128 matrix), "refined32" (complex64 fill written twice, FP64
+    refinement against one copy) or False (complex128 throughout)."""
     mb = api.stack_models([pack(api, m) for m in models_o])
     xt = torch.from_numpy(np.asarray(x, np.float64)).cuda()
     yt = torch.from_numpy(np.asarray(y, np.float64)).cuda()
     n_ant = len(x)
     B = api.harp_port_rhs(mb, n_ant)
-    if refined:
+    Zres = None
+    if refined == "refined32":
+        Zr, Z32, info = api.harp_fill(mb, xt, yt, dtype="c64", dual=True)
+        F = api.reduced_factor(Z32)
+        finfo = F.info
+        X, rep = api.reduced_solve(F, B, Z64=Zr, tol=1e-10, max_iter=10)
+        Zres = Zr
+    elif refined:
         Z64, Z32, info = api.harp_fill(mb, xt, yt, dtype="c128", dual=True)
         F = api.reduced_factor(Z32)
         finfo = F.info
@@ -250,6 +260,8 @@ def _pipeline(api, models_o, x, y, refined=True):
     Y = api.harp_port_admittance(mb, X)
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all() and (finfo.cpu().numpy() == 0).all()
+    if keep_z:
+        return X.cpu().numpy(), Y.cpu().numpy(), rep, Zres.cpu().numpy(), B.cpu().numpy()
     return X.cpu().numpy(), Y.cpu().numpy(), rep
 
 
@@ -284,6 +296,23 @@ def test_hot_path_station_sweep_all_frequencies(api, refined):
     _check_against_oracle(wl, models, X, Y, REL_SOLVE if refined else REL_PLAIN)
     if refined:
         assert all(r["converged"] for r in rep)
+
+
+def test_hot_path_station_sweep_complex64_fill(api):
+    """The same configuration with the complex64 fill (FP32 evaluation) and
+    the FP64 residual taken against that complex64 matrix: every frequency
+    within the refined bar of the oracle, and each system at its own fixed
+    point (FP64 residual against the complex64 matrix, recomputed on the
+    host, within the refinement tolerance)."""
+    wl, models = oracle_models("station_sweep")
+    X, Y, rep, Zr, B = _pipeline(api, models, wl.x, wl.y, "refined32", keep_z=True)
+    assert all(r["converged"] for r in rep)
+    _check_against_oracle(wl, models, X, Y, REL_SOLVE)
+    for f in range(len(models)):
+        Z = Zr[f].astype(np.complex128)
+        R = B[f] - Z @ X[f]
+        rel = np.linalg.norm(R) / (np.linalg.norm(Z) * np.linalg.norm(X[f]))
+        assert rel <= 1e-10, (f, rel)
 
 
 def test_hot_path_strong_coupling(api):
