@@ -307,7 +307,8 @@ def bench_batched(args, api, torch, dev):
     layouts = batched_layouts()
     # the planner's cost model measured on this GPU (one group per point)
     cost, cost_points = api.autotune_batch_costs(mb)
-    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost, graph=not args.no_graph)
+    S = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost, graph=not args.no_graph,
+                        fill=args.fill)
     # kernel choices (panel width, GEMM tile switch) per group order, timed on this GPU
     tuning, tuning_points = api.autotune_kernels([(g.n, len(g.members), g.n_ports_pad) for g in S.groups])
     S.tuning = tuning
@@ -344,7 +345,7 @@ def bench_batched(args, api, torch, dev):
 
     # kernel-class timers need eager launches: a timed pass of the eager path
     E = api.BatchSolver(mb, layouts, tol=args.tol, streams=args.streams, cost=cost,
-                        tuning=tuning) if not args.no_graph else S
+                        tuning=tuning, fill=args.fill) if not args.no_graph else S
     E.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -373,8 +374,8 @@ def bench_batched(args, api, torch, dev):
     mfl = attribute_method_flops(prof, 1, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"]
-    roofline = roofline_from_prof(prof, 1, mfl)
-    roof = step_roofs(work, fill_flops_step)
+    roofline = roofline_from_prof(prof, 1, mfl, fill32=args.fill == "c64")
+    roof = step_roofs(work, fill_flops_step, fill32=args.fill == "c64")
 
     nm = wl.elem.n_mbf
     port_solves = float(sum(S.n_ant))
@@ -399,7 +400,8 @@ def bench_batched(args, api, torch, dev):
             "workload": ("batched layouts: 48 station layouts of 64-512 elements (disk radius "
                          "19 m x sqrt(N_a/256), 1.5 m min spacing), 8 MBFs x 64 dipole samples, 8 of "
                          "16 frequencies 50-350 MHz each (384 systems, n = 528-4056, N_a ports each); "
-                         "grouped and padded, complex64 LU on MFMA + FP64 refinement"),
+                         "grouped and padded, complex64 LU on MFMA + FP64 refinement, "
+                         + ("complex64 fill" if args.fill == "c64" else "FP64 fill")),
             "systems": S.n_systems, "groups": [(len(g.members), g.n) for g in S.groups],
             "streams": args.streams, "refine_tol": args.tol, "graph": not args.no_graph,
             "graph_sweep_budget": S.sweeps if not args.no_graph else None,

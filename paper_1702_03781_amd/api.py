@@ -901,10 +901,12 @@ def harp_port_admittance_systems(models: ModelBatch, sys: torch.Tensor, X: torch
 
 class _Group:
     """Device buffers of one padded group (refined path).  info / finfo are
-    views into the batch's shared flag array."""
+    views into the batch's shared flag array.  Zres is the matrix of the FP64
+    residual: complex128 (FP64 fill) or complex64 (complex64 fill, the second
+    copy of the fill); Z32 is the copy that is factored."""
 
     def __init__(self, models: ModelBatch, members, n_pad, model_idx, n_ant, pos, n_ports, pad_multiple, dev,
-                 flags, off):
+                 flags, off, fill32=False):
         self.members, self.n_pad = members, n_pad
         c = len(members)
         n = self.n = n_pad * models.n_mbf
@@ -913,7 +915,9 @@ class _Group:
         self.sys = systems_tensor([model_idx[i] for i in members], [n_ant[i] for i in members],
                                   [pos[i] for i in members], dev, n_ports=[n_ports[i] for i in members])
         npp = self.n_ports_pad
-        self.Z64 = colmajor(c, n, n, torch.complex128, dev)
+        self.fill32 = fill32
+        self.Zres = colmajor(c, n, n, torch.complex64 if fill32 else torch.complex128, dev)
+        self.Z64 = None if fill32 else self.Zres
         self.Z32 = colmajor(c, n, n, torch.complex64, dev)
         self.B = colmajor(c, n, npp, torch.complex128, dev)
         self.X = colmajor(c, n, npp, torch.complex128, dev)
@@ -1065,10 +1069,12 @@ def autotune_kernels(groups, reps: int = 2, seed: int = 11, widths=(16, 8, 4), s
 
 
 class BatchSolver:
-    """The refined hot path (FP64 fill written as complex128 and complex64,
-    complex64 LU, solve, FP64 refinement, admittances) for a batch of
-    unequal layouts, each at several frequencies, reusing one model per
-    frequency.  A layout is (x, y, frequency indices) or (x, y, frequency
+    """The refined hot path (fill, complex64 LU, solve, FP64 refinement,
+    admittances) for a batch of unequal layouts, each at several
+    frequencies, reusing one model per frequency.  fill="c128": FP64 fill
+    written as complex128 (the residual's matrix) and complex64 (factored);
+    fill="c64": complex64 fill written twice, the FP64 residual taken against
+    one copy (widened as it is read).  A layout is (x, y, frequency indices) or (x, y, frequency
     indices, n_ports): its ports are its first n_ports antennas (default all).
     Systems are grouped by harp_batch_plan and padded per group; groups are
     issued round-robin on `streams` HIP streams (default priority), all
@@ -1084,7 +1090,10 @@ class BatchSolver:
 
     def __init__(self, models: ModelBatch, layouts, tol: float = 1e-10, max_iter: int = 10,
                  streams: int = 1, ri: float = 0.0, graph: bool = False, sweeps: int = 3, tuning=None,
-                 **plan_kw):
+                 fill: str = "c128", **plan_kw):
+        if fill not in ("c128", "c64"):
+            raise ValueError(f"BatchSolver: fill must be 'c128' or 'c64', not {fill!r}")
+        self.fill32 = fill == "c64"
         dev = models.data.device
         self.models, self.tol, self.max_iter, self.ri = models, tol, max_iter, ri
         self.tuning = tuning
@@ -1114,7 +1123,7 @@ class BatchSolver:
         self.groups = []
         for b, e, pad in groups:
             self.groups.append(_Group(models, order[b:e], pad, model_idx, n_ant, pos, n_ports, pm, dev,
-                                      self.flags, b))
+                                      self.flags, b, fill32=self.fill32))
         self.where = {}
         for gi, g in enumerate(self.groups):
             for k, s in enumerate(g.members):
@@ -1130,11 +1139,12 @@ class BatchSolver:
     def _front(self, g: _Group, st: int):
         L, mb = lib(), self.models
         c = len(g.members)
-        pz, ldz, sz = _cm(g.Z64, "Z64")
+        pz, ldz, sz = _cm(g.Zres, "Zres")
         p32, ld32, s32 = _cm(g.Z32, "Z32")
         check(L.harp_fill_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, mb.Q, mb.p_max, _ptr(self.x),
                                   _ptr(self.y), int(self.x.numel()), _ptr(g.sys), c, g.n_pad, float(self.ri),
-                                  C128, pz, ldz, sz, p32, ld32, s32, _ptr(g.info), st), "harp_fill_systems")
+                                  C64 if g.fill32 else C128, pz, ldz, sz, p32, ld32, s32, _ptr(g.info), st),
+              "harp_fill_systems")
         pb, ldb, sb = _cm(g.B, "B")
         check(L.harp_port_rhs_systems(_ptr(mb.data), mb.stride, mb.n_freq, mb.n_mbf, _ptr(g.sys), c, g.n_pad,
                                       g.n_ports_pad, pb, ldb, sb, st), "harp_port_rhs_systems")
@@ -1144,12 +1154,12 @@ class BatchSolver:
     def _back(self, g: _Group, st: int, host: bool):
         L, mb = lib(), self.models
         c = len(g.members)
-        pz, ldz, sz = _cm(g.Z64, "Z64")
+        pz, ldz, sz = _cm(g.Zres, "Zres")
         p32, ld32, s32 = _cm(g.Z32, "Z32")
         pb, ldb, sb = _cm(g.B, "B")
         px, ldx, sx = _cm(g.X, "X")
         ref = HarpRefine(pz, ldz, sz, float(self.tol), int(self.max_iter if host else self.sweeps),
-                         _ptr(g.rep_dev))
+                         _ptr(g.rep_dev), int(g.fill32))
         rep = (HarpRefineReport * c)() if host else None
         status = L.reduced_solve(g.n, g.n_ports_pad, c, C64, p32, ld32, s32, _ptr(g.ipiv), _ptr(g.aux),
                                  g.aux_bytes, pb, ldb, sb, px, ldx, sx, ctypes.byref(ref), rep, _ptr(g.ws),
@@ -1225,10 +1235,11 @@ class BatchSolver:
         return g.X[k, :n, :npt], g.Y[k, :na, :npt], g.info[k], g.finfo[k]
 
     def padded(self, s: int):
-        """(Z64, X, Y) of system s with its padding."""
+        """(Zres, X, Y) of system s with its padding; Zres is the matrix of the
+        FP64 residual (complex128, or complex64 with fill="c64")."""
         gi, k = self.where[s]
         g = self.groups[gi]
-        return g.Z64[k], g.X[k], g.Y[k]
+        return g.Zres[k], g.X[k], g.Y[k]
 
 
 @dataclass

@@ -175,25 +175,24 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
             }
         }
         if constexpr (A32) {
-            // complex64 A: one 16-byte access holds two consecutive rows; the
-            // raw bytes wait in register slot 2 e2 and are widened only when
-            // stored (after the current chunk's products), so that the load
-            // stays in flight during them
+            // complex64 A: two consecutive rows per thread; the raw bytes wait
+            // in register slot 2 e2 and are widened only when stored (after
+            // the current chunk's products), so that the loads stay in flight
+            // during them
 #pragma unroll
             for (int e2 = 0; e2 < NA / 2; ++e2) {
                 const int v = tid + 256 * e2;
                 const int kk = v / (BM / 2), r = (v % (BM / 2)) * 2;
                 const int gk = k0 + kk, gr = row0 + r;
+                // two guarded 8-byte loads, each into its own half of the slot
+                // (one path for every case, so that nothing waits on them
+                // before the store)
                 const float2* src = Aw + size_t(gk) * g.lda + gr;
-                float4 q;
-                if (VEC && gk < g.K && gr + 2 <= g.M) {
-                    q = *reinterpret_cast<const float4*>(src);
-                } else {
-                    const float2 w0 = (gk < g.K && gr < g.M) ? src[0] : float2{0.f, 0.f};
-                    const float2 w1 = (gk < g.K && gr + 1 < g.M) ? src[1] : float2{0.f, 0.f};
-                    q = float4{w0.x, w0.y, w1.x, w1.y};
-                }
-                __builtin_memcpy(&ra[2 * e2], &q, sizeof(q));
+                const float2 w0 = (gk < g.K && gr < g.M) ? src[0] : float2{0.f, 0.f};
+                const float2 w1 = (gk < g.K && gr + 1 < g.M) ? src[1] : float2{0.f, 0.f};
+                char* slot = reinterpret_cast<char*>(&ra[2 * e2]);
+                __builtin_memcpy(slot, &w0, sizeof(w0));
+                __builtin_memcpy(slot + sizeof(w0), &w1, sizeof(w1));
             }
         }
 #pragma unroll
