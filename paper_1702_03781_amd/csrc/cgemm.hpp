@@ -157,24 +157,37 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     // global -> registers: A vector e covers rows a_r[e]..+NV-1 of k-row a_k[e];
     // B vector e covers k b_k[e]..+NV-1 of column b_c[e]
     Vec16<T> ra[NA], rb[NBv];
+    // Whether a tile's operand panels lie wholly inside the matrices, and a
+    // chunk's K range inside K, is the same for the whole workgroup: such
+    // chunks take unguarded 16-byte loads, the others guarded loads of one
+    // complex number each.  (A per-lane choice between the two would run both
+    // under lane masks into the same registers, and every load would then
+    // wait for the one before it.)
+    const bool a_full = VEC && row0 + BM <= g.M;
+    const bool b_full = VEC && col0 + BN <= g.N;
     auto load_chunk = [&](int k0, Vec16<T> (&ra)[NA], Vec16<T> (&rb)[NBv]) {
+        const bool k_full = k0 + BK <= g.K;
+        if constexpr (!A32) {
+            if (a_full && k_full) {
 #pragma unroll
-        for (int e = 0; e < NA; ++e) {
-            const int v = tid + 256 * e;
-            const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
-            const int gk = k0 + kk, gr = row0 + r;
-            if constexpr (!A32) {
-                const ct* src = A + size_t(gk) * g.lda + gr;
-                if (VEC && gk < g.K && gr + NV <= g.M) {
-                    ra[e] = *reinterpret_cast<const Vec16<T>*>(src);
-                } else {
+                for (int e = 0; e < NA; ++e) {
+                    const int v = tid + 256 * e;
+                    const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
+                    ra[e] = *reinterpret_cast<const Vec16<T>*>(A + size_t(k0 + kk) * g.lda + row0 + r);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < NA; ++e) {
+                    const int v = tid + 256 * e;
+                    const int kk = v / (BM / NV), r = (v % (BM / NV)) * NV;
+                    const int gk = k0 + kk, gr = row0 + r;
+                    const ct* src = A + size_t(gk) * g.lda + gr;
 #pragma unroll
                     for (int q = 0; q < NV; ++q)
                         ra[e].v[q] = (gk < g.K && gr + q < g.M) ? src[q] : ct{T(0), T(0)};
                 }
             }
-        }
-        if constexpr (A32) {
+        } else {
             // complex64 A: two consecutive rows per thread; the raw bytes wait
             // in register slot 2 e2 and are widened only when stored (after
             // the current chunk's products), so that the loads stay in flight
@@ -184,26 +197,33 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
                 const int v = tid + 256 * e2;
                 const int kk = v / (BM / 2), r = (v % (BM / 2)) * 2;
                 const int gk = k0 + kk, gr = row0 + r;
-                // two guarded 8-byte loads, each into its own half of the slot
-                // (one path for every case, so that nothing waits on them
-                // before the store)
                 const float2* src = Aw + size_t(gk) * g.lda + gr;
-                const float2 w0 = (gk < g.K && gr < g.M) ? src[0] : float2{0.f, 0.f};
-                const float2 w1 = (gk < g.K && gr + 1 < g.M) ? src[1] : float2{0.f, 0.f};
                 char* slot = reinterpret_cast<char*>(&ra[2 * e2]);
-                __builtin_memcpy(slot, &w0, sizeof(w0));
-                __builtin_memcpy(slot + sizeof(w0), &w1, sizeof(w1));
+                if (a_full && k_full) {
+                    const float4 q = *reinterpret_cast<const float4*>(src);
+                    __builtin_memcpy(slot, &q, sizeof(q));
+                } else {
+                    const float2 w0 = (gk < g.K && gr < g.M) ? src[0] : float2{0.f, 0.f};
+                    const float2 w1 = (gk < g.K && gr + 1 < g.M) ? src[1] : float2{0.f, 0.f};
+                    __builtin_memcpy(slot, &w0, sizeof(w0));
+                    __builtin_memcpy(slot + sizeof(w0), &w1, sizeof(w1));
+                }
             }
         }
+        if (b_full && k_full) {
 #pragma unroll
-        for (int e = 0; e < NBv; ++e) {
-            const int v = tid + 256 * e;
-            const int c = v / (BK / NV), kk = (v % (BK / NV)) * NV;
-            const int gc = col0 + c, gk = k0 + kk;
-            const ct* src = B + size_t(gc) * g.ldb + gk;
-            if (VEC && gc < g.N && gk + NV <= g.K) {
-                rb[e] = *reinterpret_cast<const Vec16<T>*>(src);
-            } else {
+            for (int e = 0; e < NBv; ++e) {
+                const int v = tid + 256 * e;
+                const int c = v / (BK / NV), kk = (v % (BK / NV)) * NV;
+                rb[e] = *reinterpret_cast<const Vec16<T>*>(B + size_t(col0 + c) * g.ldb + k0 + kk);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < NBv; ++e) {
+                const int v = tid + 256 * e;
+                const int c = v / (BK / NV), kk = (v % (BK / NV)) * NV;
+                const int gc = col0 + c, gk = k0 + kk;
+                const ct* src = B + size_t(gc) * g.ldb + gk;
 #pragma unroll
                 for (int q = 0; q < NV; ++q)
                     rb[e].v[q] = (gc < g.N && gk + q < g.K) ? src[q] : ct{T(0), T(0)};
