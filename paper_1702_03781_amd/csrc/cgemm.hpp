@@ -142,6 +142,14 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     const int row0 = tm * BM, col0 = tn * BN;
 
     const size_t a_off = size_t(bz) * g.sA + size_t(bi) * g.sA2;
+    // Whether a tile's operand panels lie wholly inside the matrices, and a
+    // chunk's K range inside K, is the same for the whole workgroup: such
+    // chunks take unguarded 16-byte loads, the others guarded loads of one
+    // complex number each.  (A per-lane choice between the two would run both
+    // under lane masks into the same registers, and every load would then
+    // wait for the one before it.)
+    const bool a_full = VEC && row0 + BM <= g.M;
+    const bool b_full = VEC && col0 + BN <= g.N;
     const ct* A = A32 ? nullptr : reinterpret_cast<const ct*>(g.A) + a_off;
     const float2* Aw = A32 ? reinterpret_cast<const float2*>(g.A32) + a_off : nullptr;
     const ct* B = reinterpret_cast<const ct*>(g.B) + size_t(bz) * g.sB + size_t(bi) * g.sB2;
@@ -157,14 +165,6 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     // global -> registers: A vector e covers rows a_r[e]..+NV-1 of k-row a_k[e];
     // B vector e covers k b_k[e]..+NV-1 of column b_c[e]
     Vec16<T> ra[NA], rb[NBv];
-    // Whether a tile's operand panels lie wholly inside the matrices, and a
-    // chunk's K range inside K, is the same for the whole workgroup: such
-    // chunks take unguarded 16-byte loads, the others guarded loads of one
-    // complex number each.  (A per-lane choice between the two would run both
-    // under lane masks into the same registers, and every load would then
-    // wait for the one before it.)
-    const bool a_full = VEC && row0 + BM <= g.M;
-    const bool b_full = VEC && col0 + BN <= g.N;
     auto load_chunk = [&](int k0, Vec16<T> (&ra)[NA], Vec16<T> (&rb)[NBv]) {
         const bool k_full = k0 + BK <= g.K;
         if constexpr (!A32) {
@@ -270,6 +270,26 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     auto add_c = [&]() {
         const T* Cr = g.C ? g.C + 2 * (size_t(bz) * g.sC + size_t(bi) * g.sC2) : nullptr;
         const bool use_c = g.beta != T(0) && Cr != nullptr;
+        if constexpr (sizeof(T) == 4) {
+            // a tile wholly inside M and N (the same for the whole workgroup):
+            // every 16-byte C access is issued before the first is used
+            if (use_c && a_full && b_full) {
+                f32x4 c4[RB][CB];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int j = 0; j < CB; ++j) {
+                        const int col = col0 + wc + j * 16 + b_col;
+                        const int r4 = 2 * (row0 + wr + i * 8) + 4 * (lane >> 4);
+                        c4[i][j] = *reinterpret_cast<const f32x4*>(Cr + 2 * size_t(col) * g.ldc + r4);
+                    }
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int j = 0; j < CB; ++j) acc[i][j] += c4[i][j] * g.beta;
+                return;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -293,7 +313,6 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
                 }
             }
     };
-    if (!PF2) add_c();
 
     // operand selection for this lane (see the header comment)
     const int s = lane & 1;
@@ -332,10 +351,11 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     const int ke = g.tri == 1 ? min(g.K, row0 + BM) : g.K;
     const int nchunks = (ke - kb + BK - 1) / BK;
     if constexpr (!PF2) {
-        if (nchunks > 0) {
-            load_chunk(kb, ra, rb);
-            store_chunk(0, ra, rb);
-        }
+        // the first chunk's loads go out before the C reads, so that the two
+        // are in flight together
+        if (nchunks > 0) load_chunk(kb, ra, rb);
+        add_c();
+        if (nchunks > 0) store_chunk(0, ra, rb);
         __syncthreads();
         for (int c = 0; c < nchunks; ++c) {
             const int buf = c & 1;
@@ -368,6 +388,19 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     }
 
     T* Dr = g.D + 2 * (size_t(bz) * g.sD + size_t(bi) * g.sD2);
+    if constexpr (sizeof(T) == 4) {
+        if (a_full && b_full) {   // whole tile: unguarded 16-byte stores
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < CB; ++j) {
+                    const int col = col0 + wc + j * 16 + b_col;
+                    const int r4 = 2 * (row0 + wr + i * 8) + 4 * (lane >> 4);
+                    *reinterpret_cast<f32x4*>(Dr + 2 * size_t(col) * g.ldd + r4) = acc[i][j];
+                }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
 #pragma unroll
