@@ -223,6 +223,7 @@ template <typename T, int NT, int W, int WT = W> struct alignas(16) PanelShared 
     T cand_v[2][NW];
     int cand_i[2][NW];
     int piv_s[WT];
+    int first_zero;   // 1 + the first column with a zero pivot (0: none)
     int cand_s[2 * WT], src_s[2 * WT];
     int cand2_s[2 * W], src2_s[2 * W];
 };
@@ -344,10 +345,11 @@ __device__ __forceinline__ void panel_columns(typename C2<T>::t (&a)[RPT][W], in
             zero = !(bv > T(0));
             p = bv >= T(0) ? bi : j;
         }
+        // the pivot and the first zero pivot stay in LDS until the panel ends
+        // (no global memory operation inside the column chain)
         if (tid == 0) {
             sh.piv_s[C0 + JJ] = p;
-            pa.ipiv[size_t(b) * n + j] = p;
-            if (zero) atomicCAS(pa.info + b, 0, j + 1);
+            if (zero && sh.first_zero == 0) sh.first_zero = j + 1;
         }
         // exchange the labels of rows j and p
 #pragma unroll
@@ -524,24 +526,39 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     int lrow[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) lrow[r] = j0 + tid + r * NT;
+    if (tid == 0) sh.first_zero = 0;
     panel_columns<T, NT, RPT, W, WT, 0, 0>(a, lrow, sh, pa, b, tid);
     const int w1 = w < W ? w : W;   // columns of the first block
     const int w2 = w - w1;          // columns of the second (0 with one block)
 
     // the first block goes back at its labels now (with two blocks the
     // second block's exchanges reach it below, like any other column); its
-    // unit-lower top stays in LDS
+    // unit-lower top stays in LDS.  A full-width block (the same for the
+    // whole workgroup) stores every column of a row in one straight run, so
+    // that each store has its own address registers and none waits for the
+    // one before it.
+    // (the LDS copy first: nothing after the global stores then waits for
+    // them to finish)
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int row = lrow[r];
+        if (row >= j0 && row < j0 + w1) {
+#pragma unroll
+            for (int c = 0; c < W; ++c) Ls[row - j0][c] = a[r][c];
+        }
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int row = lrow[r];
         if (row < n) {
+            if (w1 == W) {
 #pragma unroll
-            for (int c = 0; c < W; ++c)
-                if (c < w1) A[size_t(j0 + c) * lda + row] = a[r][c];
-        }
-        if (row >= j0 && row < j0 + w1) {
+                for (int c = 0; c < W; ++c) A[size_t(j0 + c) * lda + row] = a[r][c];
+            } else {
 #pragma unroll
-            for (int c = 0; c < W; ++c) Ls[row - j0][c] = a[r][c];
+                for (int c = 0; c < W; ++c)
+                    if (c < w1) A[size_t(j0 + c) * lda + row] = a[r][c];
+            }
         }
     }
     if constexpr (H == 2) {
@@ -610,20 +627,33 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int row = lrow[r];
-                if (row < n) {
-#pragma unroll
-                    for (int c = 0; c < W; ++c)
-                        if (c < w2) A[size_t(j0 + W + c) * lda + row] = a2[r][c];
-                }
                 if (row >= j0 && row < j0 + w) {
 #pragma unroll
                     for (int c = 0; c < W; ++c) Ls[row - j0][W + c] = a2[r][c];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int row = lrow[r];
+                if (row < n) {
+                    if (w2 == W) {
+#pragma unroll
+                        for (int c = 0; c < W; ++c) A[size_t(j0 + W + c) * lda + row] = a2[r][c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < W; ++c)
+                            if (c < w2) A[size_t(j0 + W + c) * lda + row] = a2[r][c];
+                    }
                 }
             }
         }
     }
     __syncthreads();
 
+    // the panel's pivots and its first zero pivot (LAPACK's info: the
+    // earliest column wins, and panels run in column order)
+    if (tid < w) pa.ipiv[size_t(b) * n + j0 + tid] = piv_s[tid];
+    if (tid == 0 && sh.first_zero != 0) atomicCAS(pa.info + b, 0, sh.first_zero);
     // rows touched by this panel's exchanges: the w top rows and the w pivot
     // rows; source of each after all exchanges, by walking them backwards.
     // With two blocks, the first block's columns take the second block's
