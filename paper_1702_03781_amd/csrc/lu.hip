@@ -686,14 +686,34 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     const int right = pa.kend - (j0 + w);
     const int nother = left + right;
     const int n2 = 2 * w, m2 = 2 * w2;
-    for (int e = tid; e < n2 * nother; e += NT) {
-        const int t = e % n2, oc = e / n2;
-        const int col = oc < left ? pa.k0 + oc : j0 + w + (oc - left);
-        stage[oc][t] = A[size_t(col) * lda + src_s[t]];
-    }
-    for (int e = tid; e < m2 * W; e += NT) {
-        const int t = e % m2, c = e / m2;
-        stage[nother + c][t] = A[size_t(j0 + c) * lda + sh.src2_s[t]];
+    {
+        // every load of a thread before the first of its LDS stores
+        constexpr int PER1 = (2 * WT * NBMAX + NT - 1) / NT, PER2 = (2 * W * W + NT - 1) / NT;
+        V g1[PER1], g2[PER2];
+#pragma unroll
+        for (int q = 0; q < PER1; ++q) {
+            const int e = tid + NT * q;
+            if (e < n2 * nother) {
+                const int t = e % n2, oc = e / n2;
+                const int col = oc < left ? pa.k0 + oc : j0 + w + (oc - left);
+                g1[q] = A[size_t(col) * lda + src_s[t]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER2; ++q) {
+            const int e = tid + NT * q;
+            if (e < m2 * W) g2[q] = A[size_t(j0 + e / m2) * lda + sh.src2_s[e % m2]];
+        }
+#pragma unroll
+        for (int q = 0; q < PER1; ++q) {
+            const int e = tid + NT * q;
+            if (e < n2 * nother) stage[e / n2][e % n2] = g1[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PER2; ++q) {
+            const int e = tid + NT * q;
+            if (e < m2 * W) stage[nother + e / m2][e % m2] = g2[q];
+        }
     }
     __syncthreads();
     for (int e = tid; e < n2 * nother; e += NT) {
@@ -779,9 +799,18 @@ __global__ void __launch_bounds__(256) laswp_kernel(LaswpArgs la) {
         src[tid] = map[2 * NBMAX + tid];
     }
     __syncthreads();
-    for (int e = tid; e < n2 * ncols; e += 256) {
-        const int t = e % n2, c = e / n2;
-        S[c][t] = X[size_t(c0 + c) * la.ldx + src[t]];
+    // every load of a thread is issued before the first of its LDS stores
+    constexpr int PER = (2 * NBMAX * CB + 255) / 256;
+    V v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n2 * ncols) v[q] = X[size_t(c0 + e / n2) * la.ldx + src[e % n2]];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n2 * ncols) S[e / n2][e % n2] = v[q];
     }
     __syncthreads();
     const int top_end = cand[0] + nbo;   // cand[0] is the block's first row
@@ -986,9 +1015,24 @@ __global__ void __launch_bounds__(256) group_gather_kernel(const int32_t* __rest
     const int tid = threadIdx.x;
     __shared__ V S[CG][2 * kSB + 1];
     const int n2 = 2 * sb;
-    for (int e = tid; e < n2 * ncols; e += 256) {
-        const int t = e % n2, c = e / n2;
-        S[c][t] = X[size_t(c0 + c) * ldx + src[t]];
+    // all source rows of a thread, then all its loads, then its LDS stores
+    constexpr int PER = (2 * kSB * CG + 255) / 256;
+    int sr[PER];
+    V v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        sr[q] = e < n2 * ncols ? src[e % n2] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n2 * ncols) v[q] = X[size_t(c0 + e / n2) * ldx + sr[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + 256 * q;
+        if (e < n2 * ncols) S[e / n2][e % n2] = v[q];
     }
     __syncthreads();
     for (int e = tid; e < n2 * ncols; e += 256) {
