@@ -92,6 +92,30 @@ def test_factor_and_solve_random(api, dt, n, batch):
         assert all(r["converged"] for r in rep)
 
 
+@pytest.mark.parametrize("n,batch,nrhs", [(37, 2, 5), (70, 3, 33), (129, 2, 7), (1100, 2, 19)])
+def test_refinement_against_a_complex64_matrix(api, n, batch, nrhs):
+    """FP64 refinement whose residual reads the complex64 matrix itself
+    (widened on load; odd orders and ragged K chunks take the guarded loads):
+    the result is the FP64 solution of that complex64 matrix, and its FP64
+    residual against it, recomputed on the host, is at the tolerance (plus
+    the host product's own rounding)."""
+    A = (_rand((batch, n, n), 30 + n) + 4 * np.sqrt(n) * np.eye(n)[None]).astype(np.complex64)
+    Bh = _rand((batch, n, nrhs), 40 + n)
+    Z32 = _to_cm(api, A, torch.complex64)
+    F = api.reduced_factor(_to_cm(api, A, torch.complex64))
+    B = _to_cm(api, Bh, torch.complex128)
+    X, rep = api.reduced_solve(F, B, Z64=Z32, tol=1e-13, max_iter=10)
+    torch.cuda.synchronize()
+    assert all(r["converged"] for r in rep), rep
+    A64 = A.astype(np.complex128)
+    ref = np.linalg.solve(A64, Bh)
+    Xh = X.cpu().numpy()
+    assert np.linalg.norm(Xh - ref) <= 1e-11 * np.linalg.norm(ref)
+    for b in range(batch):
+        R = Bh[b] - A64[b] @ Xh[b]
+        assert np.linalg.norm(R) <= 5e-13 * np.linalg.norm(A64[b]) * np.linalg.norm(Xh[b])
+
+
 def test_pivots_follow_partial_pivoting(api):
     """Generic matrix: the pivot sequence is LAPACK's (first max |Re|+|Im|)."""
     import scipy.linalg
