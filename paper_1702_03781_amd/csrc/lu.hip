@@ -1109,16 +1109,13 @@ inline int norm_blocks(int rows, int cols) {
     const int64_t units = int64_t((rows + 255) / 256) * cols;
     return int(std::max<int64_t>(1, std::min<int64_t>(kNormBlocks, (units + 15) / 16)));
 }
-// V0: element type of M0 (double2, or float2 for a complex64 matrix; the
-// squares are accumulated in FP64 either way); M1 is complex128
-template <typename V0>
-__global__ void __launch_bounds__(256) sumsq_partial_kernel(const V0* __restrict__ M0, int64_t ld0, int64_t s0,
+__global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __restrict__ M0, int64_t ld0, int64_t s0,
                                                             const double2* __restrict__ M1, int64_t ld1, int64_t s1,
                                                             int rows, int cols, double* __restrict__ part,
                                                             const int32_t* __restrict__ active) {
     const int b = blockIdx.z, which = blockIdx.y;
     if (active && active[b] == 0) return;
-    const V0* Ma = which ? nullptr : M0 + size_t(b) * s0;
+    const double2* Ma = which ? nullptr : M0 + size_t(b) * s0;
     const double2* Mb = which ? M1 + size_t(b) * s1 : nullptr;
     const int64_t ld = which ? ld1 : ld0;
     // four independent accumulators (four loads in flight per thread), added
@@ -1134,12 +1131,7 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const V0* __restrict
             const int c = u / chunks, r = (u % chunks) * 256 + int(threadIdx.x);
             v[q] = double2{0.0, 0.0};
             if (u < units && r < rows) {
-                if (which) {
-                    v[q] = Mb[int64_t(c) * ld + r];
-                } else {
-                    const V0 e = Ma[int64_t(c) * ld + r];
-                    v[q] = double2{double(e.x), double(e.y)};
-                }
+                v[q] = which ? Mb[int64_t(c) * ld + r] : Ma[int64_t(c) * ld + r];
             }
         }
 #pragma unroll
@@ -1153,6 +1145,54 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const V0* __restrict
     if (threadIdx.x == 0)
         part[(size_t(b) * 2 + which) * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
+// Squares of a complex64 matrix (the residual's matrix with the complex64
+// fill): two rows per 16-byte access when every column start is aligned and
+// the order even (vec2, the same for the whole launch), the raw values kept
+// until all four loads of a pass are issued; partials as above (matrix 0).
+__global__ void __launch_bounds__(256) sumsq_partial_c64_kernel(const float2* __restrict__ M, int64_t ld, int64_t s,
+                                                                int rows, int cols, bool vec2,
+                                                                double* __restrict__ part) {
+    const int b = blockIdx.z;
+    const float2* Mb = M + size_t(b) * s;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int pairs = (rows + 1) / 2;
+    const int chunks = (pairs + 255) / 256, units = chunks * cols;
+    const int G = int(gridDim.x);
+    for (int u0 = blockIdx.x; u0 < units; u0 += 4 * G) {
+        float4 raw[4];
+        if (vec2) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int u = u0 + q * G;
+                const int c = u / chunks, r = 2 * ((u % chunks) * 256 + int(threadIdx.x));
+                raw[q] = (u < units && r < rows) ? *reinterpret_cast<const float4*>(Mb + int64_t(c) * ld + r)
+                                                 : float4{0.f, 0.f, 0.f, 0.f};
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int u = u0 + q * G;
+                const int c = u / chunks, r = 2 * ((u % chunks) * 256 + int(threadIdx.x));
+                const float2* src = Mb + int64_t(c) * ld + r;
+                const float2 lo = (u < units && r < rows) ? src[0] : float2{0.f, 0.f};
+                const float2 hi = (u < units && r + 1 < rows) ? src[1] : float2{0.f, 0.f};
+                raw[q] = float4{lo.x, lo.y, hi.x, hi.y};
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double x0 = raw[q].x, y0 = raw[q].y, x1 = raw[q].z, y1 = raw[q].w;
+            acc[q] = fma(x0, x0, fma(y0, y0, fma(x1, x1, fma(y1, y1, acc[q]))));
+        }
+    }
+    double a = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[size_t(b) * 2 * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // Sum of the nblk partials p[0..nblk) by one 256-thread workgroup in a fixed
 // order (strided per thread, then a fixed tree); every thread gets the sum.
 __device__ double block_sum_partials(const double* __restrict__ p, int nblk, double* red) {
@@ -1634,16 +1674,17 @@ harp_status convert(const void* src, int64_t lds, int64_t ss, void* dst, int64_t
 // (complex64: M holds complex64 values, squared in FP64)
 harp_status fro_norms(const void* M, bool complex64, int64_t ld, int64_t s, int rows, int cols, int batch,
                       double* part, double* out, hipStream_t st) {
-    const int nblk = norm_blocks(rows, cols);
-    if (complex64)
+    int nblk = norm_blocks(rows, cols);
+    if (complex64) {
+        nblk = norm_blocks((rows + 1) / 2, cols);   // units of 256 row pairs
+        const bool vec2 = rows % 2 == 0 && ld % 2 == 0 && (batch == 1 || s % 2 == 0) &&
+                          (reinterpret_cast<uintptr_t>(M) & 15) == 0;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(sumsq_partial_kernel<float2>, dim3(nblk, 1, batch), dim3(256), 0, st,
-                                            static_cast<const float2*>(M), ld, s,
-                                            static_cast<const double2*>(nullptr), int64_t(0), int64_t(0), rows,
-                                            cols, part, static_cast<const int32_t*>(nullptr)));
-    else
+                         hipLaunchKernelGGL(sumsq_partial_c64_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
+                                            static_cast<const float2*>(M), ld, s, rows, cols, vec2, part));
+    } else
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(sumsq_partial_kernel<double2>, dim3(nblk, 1, batch), dim3(256), 0, st,
+                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
                                             static_cast<const double2*>(M), ld, s,
                                             static_cast<const double2*>(nullptr), int64_t(0), int64_t(0), rows,
                                             cols, part, static_cast<const int32_t*>(nullptr)));
@@ -1875,7 +1916,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         g.site = HARP_SITE_RESIDUAL;
         if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                         hipLaunchKernelGGL(sumsq_partial_kernel<double2>, dim3(rnblk, 2, batch), dim3(256), 0, st,
+                         hipLaunchKernelGGL(sumsq_partial_kernel, dim3(rnblk, 2, batch), dim3(256), 0, st,
                                             static_cast<const double2*>(W.R), int64_t(n), mat,
                                             static_cast<const double2*>(d_X), ldx, stride_x, n, nrhs, W.part,
                                             static_cast<const int32_t*>(W.active)));
