@@ -187,17 +187,48 @@ def class_rates(prof, steps):
     return out
 
 
-def method_flops(n, nrhs, iters, refined=True):
+def method_flops(n, nrhs, iters, refined=True, first_rows=None):
     """Algorithmic flops of one pass of the solver over len(iters) systems of
     order n with nrhs right-hand sides: LU 8n^3/3 each; triangular solves
     8 n^2 nrhs per solve (one initial solve plus one per correction); the FP64
-    residuals 8 n^2 nrhs each (one per check: one more than corrections)."""
+    residuals 8 n^2 nrhs each (one per check: one more than corrections).
+    first_rows ([systems][nrhs], optional): the first non-zero row f of each
+    column of P B; the first forward substitution of such a column starts
+    there, 4 (n - f)^2 flops instead of 4 n^2 (the sparse right-hand sides of
+    port excitations)."""
     lu = len(iters) * 8.0 * n ** 3 / 3.0
+    saved = 0.0
+    if first_rows is not None:
+        import numpy as np
+        f = np.asarray(first_rows, dtype=np.float64)
+        assert f.shape == (len(iters), nrhs)
+        saved = float(np.sum(4.0 * (n * n - (n - f) ** 2)))
     if not refined:
-        return {"lu": lu, "solves": len(iters) * 8.0 * n * n * nrhs, "residuals": 0.0}
-    solves = sum(1 + it for it in iters) * 8.0 * n * n * nrhs
+        return {"lu": lu, "solves": len(iters) * 8.0 * n * n * nrhs - saved, "residuals": 0.0}
+    solves = sum(1 + it for it in iters) * 8.0 * n * n * nrhs - saved
     resid = sum(1 + it for it in iters) * 8.0 * n * n * nrhs
     return {"lu": lu, "solves": solves, "residuals": resid}
+
+
+def rhs_first_rows(ipiv, B):
+    """First non-zero row of each column of P B, per system (n where a column
+    is zero): ipiv [systems][n] (host or torch; the row exchanged with row i
+    at step i, 0-based), B a torch tensor [systems][n][nrhs] on any device
+    (masked there; only the pivots and the result cross to the host)."""
+    import numpy as np
+    import torch
+    piv = ipiv.cpu().numpy() if isinstance(ipiv, torch.Tensor) else np.asarray(ipiv)
+    ns, n = piv.shape
+    out = np.empty((ns, B.shape[2]), dtype=np.int64)
+    for s in range(ns):
+        perm = np.arange(n)
+        for i, p in enumerate(piv[s]):
+            if p != i:
+                perm[i], perm[p] = perm[p], perm[i]
+        nz = B[s].index_select(0, torch.from_numpy(perm).to(B.device)) != 0
+        first = torch.where(nz.any(0), nz.to(torch.int32).argmax(0), torch.full_like(nz[0], n, dtype=torch.int64))
+        out[s] = first.cpu().numpy()
+    return out
 
 
 def attribute_method_flops(prof, steps, work, fill_flops_step, refined=True):
@@ -265,8 +296,9 @@ def roofline_from_prof(prof, steps, mflops, fill32=False):
         "algorithmic_flops_per_launch": mflops.get(dom, pd["flops"]) / launches,
         "algorithmic_bytes_per_launch": pd["bytes"] / launches,
         "flops_charged": "method flops: LU 8n^3/3 and triangular solves 8n^2 N_rhs per solve (measured "
-                         "sweep count), less the panel and rank-w kernels' own; FP64 residual 8n^2 N_rhs "
-                         "per check; fill 2(2P+1)(2Q+4) per model-evaluated entry",
+                         "sweep count; the first forward substitution 4(n-f)^2 per column from its first "
+                         "non-zero row f of P B), less the panel and rank-w kernels' own; FP64 residual "
+                         "8n^2 N_rhs per check; fill 2(2P+1)(2Q+4) per model-evaluated entry",
     }
 
 
@@ -360,11 +392,12 @@ def bench_batched(args, api, torch, dev):
     prof = api.prof_read()
     api.prof_enable(False)
     e_iters = [E.reports[s]["iters"] for s in range(E.n_systems)]
+    e_first = [rhs_first_rows(g.ipiv, g.B) for g in E.groups]
     del E
     fill_flops_step = 0.0
     lu = solves = resid = 0.0
-    for g in S.groups:
-        w = method_flops(g.n, g.n_ports_pad, [e_iters[m] for m in g.members])
+    for g, first in zip(S.groups, e_first):
+        w = method_flops(g.n, g.n_ports_pad, [e_iters[m] for m in g.members], first_rows=first)
         lu, solves, resid = lu + w["lu"], solves + w["solves"], resid + w["residuals"]
     for s in range(S.n_systems):
         li, f = S.layout_of[s]
@@ -486,10 +519,11 @@ def bench_large(args, api, torch, dev):
     prof = api.prof_read()
     api.prof_enable(False)
     it = [r["iters"] for r in S.reports]
+    first = rhs_first_rows(S.ipiv, S.B)
     n = wl.n
     fill_flops = fill_flops_of(wl.P, wl.Q, int(np.count_nonzero(
         (np.hypot(wl.x[:, None] - wl.x[None, :], wl.y[:, None] - wl.y[None, :]) <= wl.ri))) - wl.n_ant, wl.elem.n_mbf)
-    work = method_flops(n, wl.n_ant, it)
+    work = method_flops(n, wl.n_ant, it, first_rows=first)
     mfl = attribute_method_flops(prof, 1, work, fill_flops)
     for v in prof.values():
         v["ms_per_step"] = v["ms"]
@@ -721,6 +755,7 @@ def main():
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     per_step = sorted(step_ev[i].elapsed_time(step_ev[i + 1]) for i in range(args.steps))
     iters = [r["iters"] for r in ref.reports]
+    first_ref = rhs_first_rows(ref.ipiv, ref.B)
 
     # phases (fill + excitation, factorisation, solve + refinement, admittances)
     # from events at the phase boundaries of a few more steps
@@ -795,13 +830,13 @@ def main():
     fill_flops_step = fill_flops_of(wl.P, wl.Q, na * (na - 1), wl.elem.n_mbf)
 
 
-    work = method_flops(n, na, iters, refined=True)
+    work = method_flops(n, na, iters, refined=True, first_rows=first_ref)
     mfl = attribute_method_flops(prof, args.steps, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
     roofline = roofline_from_prof(prof, args.steps, mfl, fill32=fill32)
     roof_ref = step_roofs(work, fill_flops_step, refined=True, fill32=fill32)
-    work_plain = method_flops(n, na, [0] * nf, refined=False)
+    work_plain = method_flops(n, na, [0] * nf, refined=False, first_rows=rhs_first_rows(plain.ipiv, plain.B))
     roof_plain = step_roofs(work_plain, fill_flops_step, refined=False)
     t_fill = prof["fill"]["ms_per_step"] * 1e-3
 
@@ -887,7 +922,9 @@ def main():
                  "steps": 3, "ms_per_step": ms5, "port_solves_per_s": wl5.n_ant / (ms5 * 1e-3),
                  "reduced_z_entries_per_s": n5 * n5 / (ph5["fill_and_excitation"] * 1e-3),
                  "phase_ms": {k: round(v, 3) for k, v in ph5.items()}, "refine_iters": it5,
-                 "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5), 0.0, fill32=fill32)["ms"]}
+                 "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5,
+                                                             first_rows=rhs_first_rows(S5.ipiv, S5.B)),
+                                                0.0, fill32=fill32)["ms"]}
         X5, Y5 = S5.X[0].cpu().numpy(), S5.Y[0].cpu().numpy()
         del S5
         torch.cuda.empty_cache()

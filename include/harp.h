@@ -327,6 +327,10 @@ harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype 
  * exchanges, the inverse unit-lower block and the update of the rows below;
  * then per group backwards, the inverse upper block and the update of the rows
  * above, all products on the matrix cores.  B and X are complex128 (n x nrhs).
+ * The first forward substitution leaves out the update products of right-hand
+ * sides that are still exactly zero (their solution is zero above the first
+ * non-zero row of P B: a port excitation touching only its own antenna's rows
+ * skips most of them); the result is the same up to the sign of zeros.
  * With refine == NULL, X is the solve in the factor precision.  With refine !=
  * NULL: the residual R = B - Z X is formed in FP64 against refine->d_Z and
  * corrections are solved with the factors and added in FP64, until the

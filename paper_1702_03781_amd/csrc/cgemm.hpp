@@ -86,6 +86,12 @@ template <typename T> struct GemmArgs {
     // T = double only: A held as complex64 (A must be null), each entry
     // widened to FP64 as it is loaded; lda and sA count complex64 elements
     const float* A32 = nullptr;
+    // optional [outer batch][N] flags (batch stride s_nz), 0 where that
+    // column of B is exactly zero: a tile whose columns are all flagged 0
+    // adds an exactly zero product, so it skips the contraction (D = beta C),
+    // and an update in place (D == C, beta = 1) ends at once
+    const int32_t* b_nz = nullptr;
+    int64_t s_nz = 0;
 };
 
 template <typename T> struct alignas(16) Vec16 {
@@ -140,6 +146,15 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     const int bz = zz / g.inner, bi = zz % g.inner;
     if (g.active && g.active[bz] == 0) return;
     const int row0 = tm * BM, col0 = tn * BN;
+    bool zero_b = false;   // every wave reads the same flags: uniform
+    if (g.b_nz) {
+        const int c = col0 + int(threadIdx.x & 63);
+        const bool nz = int(threadIdx.x & 63) < BN && c < g.N && g.b_nz[size_t(bz) * g.s_nz + c] != 0;
+        zero_b = __builtin_amdgcn_ballot_w64(nz) == 0;
+        if (zero_b && g.beta == T(1) && static_cast<const void*>(g.C) == static_cast<const void*>(g.D) &&
+            g.ldc == g.ldd && g.sC == g.sD)
+            return;
+    }
 
     const size_t a_off = size_t(bz) * g.sA + size_t(bi) * g.sA2;
     // Whether a tile's operand panels lie wholly inside the matrices, and a
@@ -349,7 +364,7 @@ __global__ void __launch_bounds__(256, OCC) cgemm_kernel(GemmArgs<T> g) {
     // contraction range of this tile row (row0 and row0 + BM are multiples of BK)
     const int kb = g.tri == 2 ? min(g.K, row0) : 0;
     const int ke = g.tri == 1 ? min(g.K, row0 + BM) : g.K;
-    const int nchunks = (ke - kb + BK - 1) / BK;
+    const int nchunks = zero_b ? 0 : (ke - kb + BK - 1) / BK;
     if constexpr (!PF2) {
         // the first chunk's loads go out before the C reads, so that the two
         // are in flight together
@@ -502,6 +517,8 @@ inline harp_status cgemm(const GemmArgs<T>& g, int batch, hipStream_t stream, in
     const double nb = double(eff_batch < 0 ? batch : eff_batch) * g.inner;
     // algorithmic bytes: A and B read once, C read when beta != 0, D written
     if (g.A32 && (sizeof(T) != 8 || g.A)) return HARP_E_ARG;
+    // zero-column flags are per outer matrix
+    if (g.b_nz && g.inner != 1) return HARP_E_ARG;
     const bool reads_c = g.beta != T(0) && g.C != nullptr;
     const double a_bytes = g.A32 ? 8.0 : 2.0 * sizeof(T);
     const double bytes = nb * (a_bytes * double(g.M) * g.K +

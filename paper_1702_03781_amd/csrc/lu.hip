@@ -993,7 +993,9 @@ __global__ void __launch_bounds__(256) group_perm_kernel(const int32_t* __restri
 }
 
 // rows [g0, g0 + sb) of X after the group's row exchanges go to Tm (ld SB);
-// rows the exchanges push below the group are written back into X
+// rows the exchanges push below the group are written back into X; with
+// colnz, colnz[b * nrhs + c] records whether column c of Tm holds a non-zero
+// (a NaN counts as one)
 // right-hand sides per gather workgroup: many small workgroups (the gathered
 // rows are latency-bound scattered reads; 16 per workgroup took 2x as long)
 constexpr int kGatherCols = 2;
@@ -1001,7 +1003,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) group_gather_kernel(const int32_t* __restrict__ perm, int G, int g, int sb,
                                                            T* __restrict__ Xr, int64_t ldx, int64_t sX, int nrhs,
                                                            T* __restrict__ Tr, int64_t sT,
-                                                           const int32_t* __restrict__ active) {
+                                                           const int32_t* __restrict__ active,
+                                                           int32_t* __restrict__ colnz) {
     using V = typename C2<T>::t;
     constexpr int CG = kGatherCols;
     const int b = blockIdx.y;
@@ -1035,6 +1038,16 @@ __global__ void __launch_bounds__(256) group_gather_kernel(const int32_t* __rest
         if (e < n2 * ncols) S[e / n2][e % n2] = v[q];
     }
     __syncthreads();
+    if (colnz) {
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            bool nz = false;
+            if (c < ncols)
+                for (int t = tid; t < sb; t += 256) nz |= S[c][t].x != T(0) || S[c][t].y != T(0);
+            const int any = __syncthreads_or(nz);
+            if (tid == 0 && c < ncols) colnz[size_t(b) * nrhs + c0 + c] = any;
+        }
+    }
     for (int e = tid; e < n2 * ncols; e += 256) {
         const int t = e % n2, c = e / n2;
         if (t < sb) {
@@ -1585,7 +1598,14 @@ harp_status tri_inverse(int n, int batch, const T* LU, int64_t lda, int64_t sA, 
 // upper block, update the rows above.  Tm: SB x nrhs per matrix.
 template <typename T>
 harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int64_t sL, const T* aux, T* X,
-                       int64_t ldx, int64_t sX, T* Tm, const int32_t* active, hipStream_t st) {
+                       int64_t ldx, int64_t sX, T* Tm, const int32_t* active, int32_t* colnz, hipStream_t st) {
+    // colnz (optional, [batch][nrhs]): the forward substitution skips the
+    // products of tiles whose right-hand sides are exactly zero in the
+    // group's rows (the diagonal block's product then stores zeros, the
+    // update leaves the rows below as they are).  The solution of L Y = P B is zero above the first non-zero row
+    // of each column of P B, so right-hand sides that start low (port
+    // excitations touch only their own antenna's rows) leave most of the
+    // early groups' updates out.
     const int G = n_groups(n);
     const int64_t sT = int64_t(kSB) * nrhs;
     const int32_t* perm = aux_perm(const_cast<T*>(aux), n, batch);
@@ -1593,9 +1613,12 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
     const int small_grid = tuning_for<T>(n).small_grid;
     harp_status s;
     auto gemm = [&](int site, int M, int N, int K, const T* A, int64_t lda_, int64_t sA_, const T* B, int64_t ldb_,
-                    int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta, int tri = 0) {
+                    int64_t sB_, T* D, int64_t ldd_, int64_t sD_, T alpha, T beta, int tri = 0,
+                    const int32_t* b_nz = nullptr) {
         GemmArgs<T> g{};
         g.tri = tri;
+        g.b_nz = b_nz;
+        g.s_nz = nrhs;
         g.M = M;
         g.N = N;
         g.K = K;
@@ -1615,7 +1638,10 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
         g.beta = beta;
         g.active = active;
         g.site = site;
-        g.small_grid = small_grid;
+        // with zero-column skipping, 32-column tiles: a tile's right-hand
+        // sides then start in the same 256-row group more often (32 ports of
+        // 8 rows), and the tiles left to run spread over more workgroups
+        g.small_grid = b_nz ? INT_MAX : small_grid;
         return cgemm<T>(g, batch, st);
     };
     for (int gi = 0; gi < G; ++gi) {
@@ -1623,16 +1649,16 @@ harp_status solve_impl(int n, int nrhs, int batch, const T* LU, int64_t lda, int
         HARP_PROF_LAUNCH(HARP_K_TRSM_L, st, 0.0, 0.0,
                          hipLaunchKernelGGL((group_gather_kernel<T>),
                                             dim3((nrhs + kGatherCols - 1) / kGatherCols, batch), dim3(256), 0, st,
-                                            perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active));
+                                            perm, G, gi, sb, X, ldx, sX, nrhs, Tm, sT, active, colnz));
         HARP_LAUNCH_CHECK();
         const T* Linv = aux + 2 * (int64_t(gi) * kRec);
         // the inverse blocks are exactly triangular: their zero halves are skipped
         if ((s = gemm(HARP_SITE_SOLVE_DIAG, sb, nrhs, sb, Linv, kSB, G * kRec, Tm, kSB, sT, X + 2 * size_t(g0), ldx, sX,
-                      T(1), T(0), 1)) != HARP_OK)
+                      T(1), T(0), 1, colnz)) != HARP_OK)
             return s;
         if (gend < n &&
             (s = gemm(HARP_SITE_SOLVE_UPDATE, n - gend, nrhs, sb, LU + 2 * (size_t(g0) * lda + gend), lda, sL, X + 2 * size_t(g0), ldx, sX,
-                      X + 2 * size_t(gend), ldx, sX, T(-1), T(1))) != HARP_OK)
+                      X + 2 * size_t(gend), ldx, sX, T(-1), T(1), 0, colnz)) != HARP_OK)
             return s;
     }
     for (int gi = G - 1; gi >= 0; --gi) {
@@ -1703,6 +1729,7 @@ struct SolveWs {
     double* znorm;    // [batch]: ||Z||_F
     int32_t* active;  // [batch]
     harp_refine_report* rep;   // [batch]
+    int32_t* colnz;   // [batch][nrhs]: non-zero columns of a group's right-hand sides (first solve)
 };
 
 size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveWs* w, char* base) {
@@ -1722,6 +1749,7 @@ size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveW
     W.znorm = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 8 : 0));
     W.active = reinterpret_cast<int32_t*>(take(refine ? int64_t(batch) * 4 : 0));
     W.rep = reinterpret_cast<harp_refine_report*>(take(refine ? int64_t(batch) * int64_t(sizeof(harp_refine_report)) : 0));
+    W.colnz = reinterpret_cast<int32_t*>(take(int64_t(batch) * nrhs * 4));
     return size_t(off);
 }
 
@@ -1838,7 +1866,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
                 return q;
             if ((q = solve_impl<float>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const float*>(d_aux),
                                        reinterpret_cast<float*>(W.B32), n, mat, static_cast<float*>(W.Tm), act,
-                                       st)) != HARP_OK)
+                                       accumulate ? nullptr : W.colnz, st)) != HARP_OK)
                 return q;
             if (accumulate) {
                 HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
@@ -1853,7 +1881,7 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         if (accumulate) {   // rhs is the residual W.R: solve it in place, then add
             if ((q = solve_impl<double>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const double*>(d_aux),
                                         reinterpret_cast<double*>(W.R), n, mat, static_cast<double*>(W.Tm), act,
-                                        st)) != HARP_OK)
+                                        nullptr, st)) != HARP_OK)
                 return q;
             HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                              hipLaunchKernelGGL(axpy_kernel<double2>, dim3(blocks, 1, batch), dim3(256), 0, st, Xd,
@@ -1864,7 +1892,8 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         if ((q = convert<double2, double2>(rhs, ldr, sr, Xd, ldx, stride_x, n, nrhs, batch, act, st)) != HARP_OK)
             return q;
         return solve_impl<double>(n, nrhs, batch, LU, lda, stride_lu, static_cast<const double*>(d_aux),
-                                  reinterpret_cast<double*>(Xd), ldx, stride_x, static_cast<double*>(W.Tm), act, st);
+                                  reinterpret_cast<double*>(Xd), ldx, stride_x, static_cast<double*>(W.Tm), act,
+                                  W.colnz, st);
     };
 
     if ((s = solve_into(d_B, ldb, stride_b, nullptr, false)) != HARP_OK) return s;

@@ -154,3 +154,36 @@ def test_fill_flops_per_entry(P, Q):
 def test_fill_flops_of_known_orders():
     assert bench.fill_flops_of([5], 3, 1, 1) == 2.0 * 11 * 10
     assert bench.fill_flops_of([5, 7], 3, 10, 4) == (2.0 * 11 * 10 + 2.0 * 15 * 10) * 10 * 16
+
+
+def _fwd_muladds_from(n, f):
+    """Complex multiply-adds of a forward substitution whose right-hand side
+    is zero above row f: rows f..n-1, each against the rows before it from f."""
+    return sum(i - f for i in range(f, n))
+
+
+@pytest.mark.parametrize("n,f", [(64, 0), (64, 17), (2048, 256), (2048, 2048)])
+def test_sparse_first_solve_charge(n, f):
+    # the first forward substitution of a column starting at row f is charged
+    # 4 (n - f)^2, the leading term of its count (n - f)(n - f - 1)/2
+    dense = bench.method_flops(n, 1, [1])
+    sparse = bench.method_flops(n, 1, [1], first_rows=[[f]])
+    charged_fwd = 4.0 * n * n - (dense["solves"] - sparse["solves"])
+    assert charged_fwd == 4.0 * (n - f) ** 2
+    assert charged_fwd - 8.0 * _fwd_muladds_from(n, f) == 4.0 * (n - f)
+    assert sparse["lu"] == dense["lu"] and sparse["residuals"] == dense["residuals"]
+
+
+def test_first_rows_follow_the_row_exchanges():
+    torch = pytest.importorskip("torch")
+    # rows 0..5; columns start at rows 1, 4 and nowhere
+    B = torch.zeros((1, 6, 3), dtype=torch.complex128)
+    B[0, 1, 0] = 1.0
+    B[0, 5, 0] = 2.0
+    B[0, 4, 1] = 1.0j
+    # step 0 exchanges rows 0 and 4, step 1 rows 1 and 5: P B puts row 4 at
+    # 0 and row 5 at 1, row 0 at 4 and row 1 at 5
+    ipiv = [[4, 5, 2, 3, 4, 5]]
+    f = bench.rhs_first_rows(ipiv, B)
+    assert f.tolist() == [[1, 0, 6]]
+    assert bench.rhs_first_rows([[0, 1, 2, 3, 4, 5]], B).tolist() == [[1, 4, 6]]
