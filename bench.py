@@ -783,6 +783,7 @@ def main():
 
     _say(f"refined {ms:.3f} ms per step; kernel timers done")
     ms_plain = None if args.no_plain else timed(plain, max(3, args.steps // 4))
+    first_plain = rhs_first_rows(plain.ipiv, plain.B)
     # the other precision of the fill and residual matrix, for comparison
     alt = api.StationSolver(mb, x, y, alt_mode, tol=args.tol)
     Xa, Ya = alt.step()
@@ -836,7 +837,7 @@ def main():
         v["ms_per_step"] = v["ms"] / args.steps
     roofline = roofline_from_prof(prof, args.steps, mfl, fill32=fill32)
     roof_ref = step_roofs(work, fill_flops_step, refined=True, fill32=fill32)
-    work_plain = method_flops(n, na, [0] * nf, refined=False, first_rows=rhs_first_rows(plain.ipiv, plain.B))
+    work_plain = method_flops(n, na, [0] * nf, refined=False, first_rows=first_plain)
     roof_plain = step_roofs(work_plain, fill_flops_step, refined=False)
     t_fill = prof["fill"]["ms_per_step"] * 1e-3
 
