@@ -246,11 +246,13 @@ def attribute_method_flops(prof, steps, work, fill_flops_step, refined=True):
     return out
 
 
-def roofline_from_prof(prof, steps, mflops, fill32=False):
+def roofline_from_prof(prof, steps, mflops, fill32=False, stored_traffic=False):
     """Roofline of the kernel class with the largest summed time, from the
     library's dispatch-attached kernel timers, charged with the method's own
     flops (mflops: per class over the timed steps; fill32: the fill runs in
-    FP32)."""
+    FP32).  stored_traffic: report the HBM bytes per launch stored in
+    profiles/traffic.json (counters taken on the station sweep, so only that
+    workload's launches match them; null while the sources differ)."""
     cand = {k: v for k, v in prof.items() if k in ("fill", "gemm_c64", "gemm_c128", "getf2",
                                                     "trsm_lower", "trsm_upper", "rank_update")}
     dom = max(cand, key=lambda k: cand[k]["ms"])
@@ -276,7 +278,7 @@ def roofline_from_prof(prof, steps, mflops, fill32=False):
         bound, peak, unit, achieved = "latency", None, "TFLOP/s", None
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf) and dom in KERNEL_SOURCES:
+    if stored_traffic and os.path.exists(tf) and dom in KERNEL_SOURCES:
         try:
             t = json.load(open(tf)).get(dom)
             if t and t.get("source_sha") == _sha(KERNEL_SOURCES[dom]):
@@ -835,7 +837,7 @@ def main():
     mfl = attribute_method_flops(prof, args.steps, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
-    roofline = roofline_from_prof(prof, args.steps, mfl, fill32=fill32)
+    roofline = roofline_from_prof(prof, args.steps, mfl, fill32=fill32, stored_traffic=True)
     roof_ref = step_roofs(work, fill_flops_step, refined=True, fill32=fill32)
     work_plain = method_flops(n, na, [0] * nf, refined=False, first_rows=first_plain)
     roof_plain = step_roofs(work_plain, fill_flops_step, refined=False)

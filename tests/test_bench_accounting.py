@@ -106,10 +106,17 @@ def test_stored_traffic_is_reported_only_for_unchanged_sources():
         pytest.skip("no stored counter figures")
     stored = json.load(open(tf))
     prof = _prof(gemm_c64={"ms": 1.0, "launches": 1, "flops": 1.0})
-    r = bench.roofline_from_prof(prof, 1, {"gemm_c64": 1.0e9})
+    r = bench.roofline_from_prof(prof, 1, {"gemm_c64": 1.0e9}, stored_traffic=True)
     t = stored.get("gemm_c64")
     fresh = t is not None and t.get("source_sha") == bench._sha(bench.KERNEL_SOURCES["gemm_c64"])
     assert r["traffic"] == (t["hbm_bytes_per_launch"] if fresh else None)
+
+
+def test_stored_traffic_belongs_to_the_station_sweep_only():
+    # the stored counters were taken on the station sweep's launches; other
+    # workloads (batched, large, tessellated) report no traffic
+    prof = _prof(gemm_c64={"ms": 1.0, "launches": 1, "flops": 1.0})
+    assert bench.roofline_from_prof(prof, 1, {"gemm_c64": 1.0e9})["traffic"] is None
 
 
 def test_step_roofs_of_the_station_sweep():
