@@ -116,6 +116,70 @@ def test_refinement_against_a_complex64_matrix(api, n, batch, nrhs):
         assert np.linalg.norm(R) <= 5e-13 * np.linalg.norm(A64[b]) * np.linalg.norm(Xh[b])
 
 
+def _sparse_rhs(perm, nrhs, seed):
+    """Right-hand sides placed by their rows' positions in P B (perm: row i of
+    P B is row perm[i] of B): columns 0-31 are non-zero only at positions in
+    the last, ragged group, columns 32-63 only in the second group (whole
+    32-column tiles that start late), column 64 is zero, column 65 has 24
+    entries anywhere, the rest one entry each at an early position."""
+    n = perm.size
+    rng = np.random.default_rng(seed)
+    B = np.zeros((n, nrhs), np.complex128)
+    groups = [(1024, n)] * 32 + [(256, 512)] * 32 + [None, (0, n)]
+    for c in range(nrhs):
+        span = groups[c] if c < len(groups) else (c, c + 1)
+        if span is None:
+            continue
+        lo, hi = span
+        pos = np.arange(lo, hi) if hi - lo < 8 else rng.choice(np.arange(lo, hi), size=min(hi - lo, 24), replace=False)
+        B[perm[pos], c] = rng.standard_normal(pos.size) + 1j * rng.standard_normal(pos.size)
+    return B
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sparse_right_hand_sides_with_row_exchanges(api, dtype):
+    """The first forward substitution leaves out the products of right-hand
+    sides that are still exactly zero in a group's rows (whole 32-column
+    tiles).  A general matrix, whose pivots move rows between the 256-row
+    groups, at a ragged order, with right-hand-side tiles placed by LAPACK's
+    row order to start in the last or the second group: every column agrees
+    with LAPACK, and the zero column's solution is exactly zero."""
+    import scipy.linalg
+    n, batch, nrhs = 1100, 2, 70
+    A = _rand((batch, n, n), 61)
+    Bh = np.empty((batch, n, nrhs), np.complex128)
+    for b in range(batch):
+        _, piv = scipy.linalg.lu_factor(A[b])
+        perm = np.arange(n)
+        for i, p in enumerate(piv):
+            perm[i], perm[p] = perm[p], perm[i]
+        assert np.abs(perm // 256 - np.arange(n) // 256).max() >= 2   # rows cross groups
+        Bh[b] = _sparse_rhs(perm, nrhs, 70 + b)
+    B = _to_cm(api, Bh, torch.complex128)
+    if dtype == "c128":
+        F = api.reduced_factor(_to_cm(api, A, torch.complex128))
+        X, _ = api.reduced_solve(F, B)
+        A_ref, tol = A, 1e-9
+    else:
+        A32 = A.astype(np.complex64)
+        F = api.reduced_factor(_to_cm(api, A32, torch.complex64))
+        X, rep = api.reduced_solve(F, B, Z64=_to_cm(api, A32, torch.complex64), tol=1e-13, max_iter=10)
+        assert all(r["converged"] for r in rep), rep
+        # forward error up to cond (1.4e3-4.0e3 here) x the 1e-13 residual; a
+        # skipped product that was not zero would leave O(1) errors
+        A_ref, tol = A32.astype(np.complex128), 1e-8
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    for b in range(batch):
+        ref = np.linalg.solve(A_ref[b], Bh[b])
+        for c in range(nrhs):
+            if c == 64:
+                assert not np.any(Xh[b][:, c]), "zero right-hand side"
+                continue
+            err = np.linalg.norm(Xh[b][:, c] - ref[:, c]) / np.linalg.norm(ref[:, c])
+            assert err <= tol, (b, c, err)
+
+
 def test_pivots_follow_partial_pivoting(api):
     """Generic matrix: the pivot sequence is LAPACK's (first max |Re|+|Im|)."""
     import scipy.linalg
