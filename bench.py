@@ -187,11 +187,13 @@ def class_rates(prof, steps):
     return out
 
 
-def method_flops(n, nrhs, iters, refined=True, first_rows=None):
+def method_flops(n, nrhs, iters, refined=True, first_rows=None, residual_update=False):
     """Algorithmic flops of one pass of the solver over len(iters) systems of
     order n with nrhs right-hand sides: LU 8n^3/3 each; triangular solves
-    8 n^2 nrhs per solve (one initial solve plus one per correction); the FP64
-    residuals 8 n^2 nrhs each (one per check: one more than corrections).
+    8 n^2 nrhs per solve (one initial solve plus one per correction); the
+    residuals 8 n^2 nrhs each (one per check: one more than corrections), in
+    FP64, except, with residual_update (a complex64 matrix), the check after
+    the first correction: a complex64 update R - Z D ("residual_updates").
     first_rows ([systems][nrhs], optional): the first non-zero row f of each
     column of P B; the first forward substitution of such a column starts
     there, 4 (n - f)^2 flops instead of 4 n^2 (the sparse right-hand sides of
@@ -204,10 +206,13 @@ def method_flops(n, nrhs, iters, refined=True, first_rows=None):
         assert f.shape == (len(iters), nrhs)
         saved = float(np.sum(4.0 * (n * n - (n - f) ** 2)))
     if not refined:
-        return {"lu": lu, "solves": len(iters) * 8.0 * n * n * nrhs - saved, "residuals": 0.0}
+        return {"lu": lu, "solves": len(iters) * 8.0 * n * n * nrhs - saved, "residuals": 0.0,
+                "residual_updates": 0.0}
     solves = sum(1 + it for it in iters) * 8.0 * n * n * nrhs - saved
-    resid = sum(1 + it for it in iters) * 8.0 * n * n * nrhs
-    return {"lu": lu, "solves": solves, "residuals": resid}
+    per = 8.0 * n * n * nrhs
+    upd = sum(1 for it in iters if it >= 1) if residual_update else 0
+    resid = (sum(1 + it for it in iters) - upd) * per
+    return {"lu": lu, "solves": solves, "residuals": resid, "residual_updates": upd * per}
 
 
 def rhs_first_rows(ipiv, B):
@@ -234,11 +239,12 @@ def rhs_first_rows(ipiv, B):
 def attribute_method_flops(prof, steps, work, fill_flops_step, refined=True):
     """Method flops per kernel class over the timed steps: the FP32 (or FP64)
     matrix-core class takes the LU and solve flops that the panel and rank-w
-    update kernels do not do themselves; the FP64 class of the refined path
-    the residuals; the fill its Eq. 4 flops."""
+    update kernels do not do themselves, and the complex64 residual updates;
+    the FP64 class of the refined path the FP64 residuals; the fill its Eq. 4
+    flops."""
     lu_cls = "gemm_c64" if refined else "gemm_c128"
     other = prof["getf2"]["flops"] + prof["rank_update"]["flops"]
-    out = {lu_cls: (work["lu"] + work["solves"]) * steps - other,
+    out = {lu_cls: (work["lu"] + work["solves"] + work.get("residual_updates", 0.0)) * steps - other,
            "getf2": prof["getf2"]["flops"], "rank_update": prof["rank_update"]["flops"],
            "fill": fill_flops_step * steps}
     if refined:
@@ -299,18 +305,19 @@ def roofline_from_prof(prof, steps, mflops, fill32=False, stored_traffic=False):
         "algorithmic_bytes_per_launch": pd["bytes"] / launches,
         "flops_charged": "method flops: LU 8n^3/3 and triangular solves 8n^2 N_rhs per solve (measured "
                          "sweep count; the first forward substitution 4(n-f)^2 per column from its first "
-                         "non-zero row f of P B), less the panel and rank-w kernels' own; FP64 residual "
-                         "8n^2 N_rhs per check; fill 2(2P+1)(2Q+4) per model-evaluated entry",
+                         "non-zero row f of P B), less the panel and rank-w kernels' own; residual 8n^2 "
+                         "N_rhs per check (FP64, or on the FP32 matrix cores for the complex64 update after "
+                         "the first correction); fill 2(2P+1)(2Q+4) per model-evaluated entry",
     }
 
 
 def step_roofs(work, fill_flops, refined=True, fill32=False):
     """Time of one step if every part ran at its roof: FP32 matrix cores for
-    the complex64 LU and solves (FP64 for the plain path), FP64 matrix cores
-    for the residuals, FP64 vector units for the fill (FP32 vector units for
-    the complex64 fill)."""
+    the complex64 LU, solves and residual updates (FP64 for the plain path),
+    FP64 matrix cores for the FP64 residuals, FP64 vector units for the fill
+    (FP32 vector units for the complex64 fill)."""
     lu_peak = PEAK["fp32_mfma_tflops"] if refined else PEAK["fp64_mfma_tflops"]
-    t_lu = (work["lu"] + work["solves"]) / (lu_peak * 1e12)
+    t_lu = (work["lu"] + work["solves"] + work.get("residual_updates", 0.0)) / (lu_peak * 1e12)
     t_res = work["residuals"] / (PEAK["fp64_mfma_tflops"] * 1e12)
     fill_peak = PEAK["fp32_vector_tflops"] if fill32 else PEAK["fp64_vector_tflops"]
     t_fill = fill_flops / (fill_peak * 1e12)
@@ -397,15 +404,17 @@ def bench_batched(args, api, torch, dev):
     e_first = [rhs_first_rows(g.ipiv, g.B) for g in E.groups]
     del E
     fill_flops_step = 0.0
-    lu = solves = resid = 0.0
+    lu = solves = resid = upd = 0.0
     for g, first in zip(S.groups, e_first):
-        w = method_flops(g.n, g.n_ports_pad, [e_iters[m] for m in g.members], first_rows=first)
+        w = method_flops(g.n, g.n_ports_pad, [e_iters[m] for m in g.members], first_rows=first,
+                         residual_update=args.fill == "c64")
         lu, solves, resid = lu + w["lu"], solves + w["solves"], resid + w["residuals"]
+        upd += w["residual_updates"]
     for s in range(S.n_systems):
         li, f = S.layout_of[s]
         na_s = S.n_ant[s]
         fill_flops_step += fill_flops_of([wl.P[f]], wl.Q, na_s * (na_s - 1), wl.elem.n_mbf)
-    work = {"lu": lu, "solves": solves, "residuals": resid}
+    work = {"lu": lu, "solves": solves, "residuals": resid, "residual_updates": upd}
     mfl = attribute_method_flops(prof, 1, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"]
@@ -525,7 +534,7 @@ def bench_large(args, api, torch, dev):
     n = wl.n
     fill_flops = fill_flops_of(wl.P, wl.Q, int(np.count_nonzero(
         (np.hypot(wl.x[:, None] - wl.x[None, :], wl.y[:, None] - wl.y[None, :]) <= wl.ri))) - wl.n_ant, wl.elem.n_mbf)
-    work = method_flops(n, wl.n_ant, it, first_rows=first)
+    work = method_flops(n, wl.n_ant, it, first_rows=first, residual_update=args.fill == "c64")
     mfl = attribute_method_flops(prof, 1, work, fill_flops)
     for v in prof.values():
         v["ms_per_step"] = v["ms"]
@@ -833,7 +842,7 @@ def main():
     fill_flops_step = fill_flops_of(wl.P, wl.Q, na * (na - 1), wl.elem.n_mbf)
 
 
-    work = method_flops(n, na, iters, refined=True, first_rows=first_ref)
+    work = method_flops(n, na, iters, refined=True, first_rows=first_ref, residual_update=fill32)
     mfl = attribute_method_flops(prof, args.steps, work, fill_flops_step, refined=True)
     for v in prof.values():
         v["ms_per_step"] = v["ms"] / args.steps
@@ -885,7 +894,8 @@ def main():
             "step_at_roofs_ms": roof_plain["ms"], "step_roof_frac": roof_plain["ms"] / ms_plain},
         "step_roofline": {**{k: round(v, 4) for k, v in roof_ref.items()}, "measured_ms": ms,
                           "frac": roof_ref["ms"] / ms,
-                          "parts": ("FP32 matrix cores: LU + solves; FP64 matrix cores: residuals; "
+                          "parts": ("FP32 matrix cores: LU + solves (+ complex64 residual updates); "
+                                    "FP64 matrix cores: FP64 residuals; "
                                     + ("FP32 vector: fill" if fill32 else "FP64 vector: fill"))},
         "phases_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in prof.items()},
         "kernel_classes": class_rates(prof, args.steps),
@@ -926,7 +936,8 @@ def main():
                  "reduced_z_entries_per_s": n5 * n5 / (ph5["fill_and_excitation"] * 1e-3),
                  "phase_ms": {k: round(v, 3) for k, v in ph5.items()}, "refine_iters": it5,
                  "step_at_roofs_ms": step_roofs(method_flops(n5, wl5.n_ant, it5,
-                                                             first_rows=rhs_first_rows(S5.ipiv, S5.B)),
+                                                             first_rows=rhs_first_rows(S5.ipiv, S5.B),
+                                                             residual_update=fill32),
                                                 0.0, fill32=fill32)["ms"]}
         X5, Y5 = S5.X[0].cpu().numpy(), S5.Y[0].cpu().numpy()
         del S5

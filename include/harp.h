@@ -310,13 +310,24 @@ typedef struct {
     int32_t z_complex64; /* 0: d_Z is complex128; 1: d_Z is complex64, each
                             entry widened to FP64 as the residual reads it
                             (the refinement then converges to the solution
-                            of that complex64 matrix) */
+                            of that complex64 matrix).  With complex64
+                            factors too, the check after the first
+                            correction D (complex64, added to X in FP64)
+                            updates the residual instead, R - Z D, with
+                            complex64 products over at most 8 K slices
+                            added in FP64; it counts as converged only when
+                            ||R||_F plus the update's error bound
+                            (sqrt(2) gamma_{2 Ks + 2} ||Z||_F ||D||_F, Ks
+                            the slice length, plus the rounding of X + D)
+                            meets the tolerance, and any later check is a
+                            full FP64 residual again */
 } harp_refine;
 
 typedef struct {
     int32_t iters;       /* correction sweeps applied */
     int32_t converged;   /* 1 if the tolerance was met */
-    double resid_rel;    /* last ||B - Z X||_F / (||Z||_F ||X||_F) */
+    double resid_rel;    /* last ||B - Z X||_F / (||Z||_F ||X||_F) as computed
+                            (for an updated residual: without its bound) */
 } harp_refine_report;
 
 harp_status reduced_solve_ws(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,

@@ -50,7 +50,8 @@ typedef enum {
     HARP_SITE_SOLVE_DIAG = 6,     /* solve: a group's inverse diagonal block */
     HARP_SITE_SOLVE_UPDATE = 7,   /* solve: update of the rows below / above a group */
     HARP_SITE_RESIDUAL = 8,       /* refinement residual B - Z X */
-    HARP_SITE_COUNT = 9
+    HARP_SITE_RESIDUAL_UPDATE = 9, /* refinement: Z D of a correction (complex64, K slices) */
+    HARP_SITE_COUNT = 10
 } harp_gemm_site;
 
 /* on != 0: clear the records and start recording; on == 0: stop. */

@@ -1333,7 +1333,7 @@ PROF_CLASSES = ["fill", "getf2", "trsm_lower", "trsm_upper", "gemm_c64", "gemm_c
 
 
 GEMM_SITES = ["other", "trailing", "catch_up", "deferred_rows", "block_row", "tri_inverse", "solve_diag",
-              "solve_update", "residual"]
+              "solve_update", "residual", "residual_update"]
 
 
 def prof_read_sites() -> dict:

@@ -1116,6 +1116,7 @@ __global__ void __launch_bounds__(256) axpy_kernel(double2* __restrict__ X, int6
 // solution of a refinement sweep take one launch; matrices whose `active`
 // flag is 0 are skipped.
 constexpr int kNormBlocks = 1024;
+constexpr int kNormSlots = 3;   // partials per matrix: residual, solution, correction
 // blocks per matrix: about 16 units (256-row column chunks) per block, at most
 // kNormBlocks, so that one large matrix still spreads over the whole chip
 inline int norm_blocks(int rows, int cols) {
@@ -1156,16 +1157,19 @@ __global__ void __launch_bounds__(256) sumsq_partial_kernel(const double2* __res
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
     if (threadIdx.x == 0)
-        part[(size_t(b) * 2 + which) * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        part[(size_t(b) * kNormSlots + which) * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 // Squares of a complex64 matrix (the residual's matrix with the complex64
-// fill): two rows per 16-byte access when every column start is aligned and
-// the order even (vec2, the same for the whole launch), the raw values kept
-// until all four loads of a pass are issued; partials as above (matrix 0).
+// fill, or a complex64 correction): two rows per 16-byte access when every
+// column start is aligned and the order even (vec2, the same for the whole
+// launch), the raw values kept until all four loads of a pass are issued;
+// partials as above, into `slot`; matrices whose `active` flag is 0 skipped.
 __global__ void __launch_bounds__(256) sumsq_partial_c64_kernel(const float2* __restrict__ M, int64_t ld, int64_t s,
                                                                 int rows, int cols, bool vec2,
-                                                                double* __restrict__ part) {
+                                                                double* __restrict__ part, int slot,
+                                                                const int32_t* __restrict__ active) {
     const int b = blockIdx.z;
+    if (active && active[b] == 0) return;
     const float2* Mb = M + size_t(b) * s;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int pairs = (rows + 1) / 2;
@@ -1203,7 +1207,8 @@ __global__ void __launch_bounds__(256) sumsq_partial_c64_kernel(const float2* __
     __shared__ double red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0) part[size_t(b) * 2 * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0)
+        part[(size_t(b) * kNormSlots + slot) * kNormBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Sum of the nblk partials p[0..nblk) by one 256-thread workgroup in a fixed
@@ -1223,8 +1228,34 @@ __global__ void __launch_bounds__(256) sumsq_final_kernel(const double* __restri
                                                           int nblk) {
     const int b = blockIdx.x;
     __shared__ double red[4];
-    const double sq = block_sum_partials(part + size_t(b) * 2 * kNormBlocks, nblk, red);
+    const double sq = block_sum_partials(part + size_t(b) * kNormSlots * kNormBlocks, nblk, red);
     if (threadIdx.x == 0) out[b] = sqrt(sq);
+}
+
+// R -= sum of the S complex64 slices P[s] (each n x nrhs, ld n, slice stride
+// sp), added in FP64 in slice order (the same order for every element and
+// every run); systems whose `active` flag is 0 skipped.
+__global__ void __launch_bounds__(256) residual_update_kernel(double2* __restrict__ R, int64_t ldr, int64_t sr,
+                                                              const float2* __restrict__ P, int64_t sp,
+                                                              int64_t sbp, int S, int rows, int cols,
+                                                              const int32_t* __restrict__ active) {
+    const int b = blockIdx.z;
+    if (active && active[b] == 0) return;
+    double2* Rb = R + size_t(b) * sr;
+    const float2* Pb = P + size_t(b) * sbp;
+    const int64_t total = int64_t(rows) * cols;
+    for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < total; e += int64_t(gridDim.x) * 256) {
+        const int64_t c = e / rows, r = e % rows;
+        double sx = 0.0, sy = 0.0;
+        for (int q = 0; q < S; ++q) {
+            const float2 v = Pb[q * sp + c * rows + r];
+            sx += double(v.x);
+            sy += double(v.y);
+        }
+        double2& o = Rb[c * ldr + r];
+        o.x -= sx;
+        o.y -= sy;
+    }
 }
 
 // Refinement control on the device.  Every system starts active with a
@@ -1232,28 +1263,41 @@ __global__ void __launch_bounds__(256) sumsq_final_kernel(const double* __restri
 // relative residual ||R||_F / (||Z||_F ||X||_F) and decides: converged
 // (inactive), out of sweeps (inactive), or one more correction (iteration
 // count + 1).  Kernels of the sweep skip inactive systems.
-__global__ void refine_init_kernel(int32_t* __restrict__ active, harp_refine_report* __restrict__ rep, int batch) {
+__global__ void refine_init_kernel(int32_t* __restrict__ active, harp_refine_report* __restrict__ rep,
+                                   double* __restrict__ bnd, int batch) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
     active[b] = 1;
+    bnd[b] = 0.0;
     rep[b].iters = 0;
     rep[b].converged = 0;
     rep[b].resid_rel = 0.0;
 }
-__global__ void __launch_bounds__(256) refine_check_kernel(const double* __restrict__ part, int nblk,
+// With dnblk > 0 the residual was updated with complex64 products (R = R_prev
+// - Z D): its error bound, bc ||Z||_F ||D||_F + bx ||Z||_F ||X||_F + babs, is
+// added to the system's running bound bnd[b] (a full FP64 residual resets it),
+// and the system converges only when the residual norm plus that bound meets
+// the tolerance.
+__global__ void __launch_bounds__(256) refine_check_kernel(const double* __restrict__ part, int nblk, int dnblk,
                                                            const double* __restrict__ znorm, double tol, int max_iter,
+                                                           double bc, double babs, double bx,
+                                                           double* __restrict__ bnd,
                                                            int32_t* __restrict__ active,
                                                            harp_refine_report* __restrict__ rep) {
     const int b = blockIdx.x;
     if (active[b] == 0) return;   // uniform over the workgroup
     __shared__ double red[4];
-    const double sr = block_sum_partials(part + size_t(b) * 2 * kNormBlocks, nblk, red);
-    const double sx = block_sum_partials(part + (size_t(b) * 2 + 1) * kNormBlocks, nblk, red);
+    const double sr = block_sum_partials(part + size_t(b) * kNormSlots * kNormBlocks, nblk, red);
+    const double sx = block_sum_partials(part + (size_t(b) * kNormSlots + 1) * kNormBlocks, nblk, red);
+    const double sd = dnblk > 0 ? block_sum_partials(part + (size_t(b) * kNormSlots + 2) * kNormBlocks, dnblk, red)
+                                : 0.0;
     if (threadIdx.x != 0) return;
+    bnd[b] = dnblk > 0 ? bnd[b] + bc * znorm[b] * sqrt(sd) + bx * znorm[b] * sqrt(sx) + babs : 0.0;
     const double rn = sqrt(sr), denom = znorm[b] * sqrt(sx);
     const double rel = denom > 0.0 ? rn / denom : (rn == 0.0 ? 0.0 : INFINITY);
+    const double relb = denom > 0.0 ? (rn + bnd[b]) / denom : (rn == 0.0 && bnd[b] == 0.0 ? 0.0 : INFINITY);
     rep[b].resid_rel = rel;
-    if (rel <= tol) {
+    if (relb <= tol) {
         rep[b].converged = 1;
         active[b] = 0;
     } else if (rep[b].iters >= max_iter) {
@@ -1707,7 +1751,8 @@ harp_status fro_norms(const void* M, bool complex64, int64_t ld, int64_t s, int 
                           (reinterpret_cast<uintptr_t>(M) & 15) == 0;
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                          hipLaunchKernelGGL(sumsq_partial_c64_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
-                                            static_cast<const float2*>(M), ld, s, rows, cols, vec2, part));
+                                            static_cast<const float2*>(M), ld, s, rows, cols, vec2, part, 0,
+                                            static_cast<const int32_t*>(nullptr)));
     } else
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                          hipLaunchKernelGGL(sumsq_partial_kernel, dim3(nblk, 1, batch), dim3(256), 0, st,
@@ -1721,11 +1766,27 @@ harp_status fro_norms(const void* M, bool complex64, int64_t ld, int64_t s, int 
     return HARP_OK;
 }
 
+// The residual after a correction, with complex64 factors and a complex64
+// matrix, is updated as R - Z D (D the complex64 correction just added to X):
+// Z D in res_slices(n) products over consecutive K slices of res_slice_k(n)
+// (the last one shorter), each on the FP32 matrix cores, the slices added in
+// FP64.  Each slice's products are accumulated in FP32 over at most
+// res_slice_k(n) complex terms, which bounds their error (residual_bound).
+constexpr int kResSlicesMax = 8;
+inline int res_slices(int n) { return std::max(1, std::min(kResSlicesMax, (n + 255) / 256)); }
+inline int res_slice_k(int n) {
+    const int S = res_slices(n), ks = (n + S - 1) / S;
+    return (ks + 15) / 16 * 16;
+}
+inline int res_slice_count(int n) { return (n + res_slice_k(n) - 1) / res_slice_k(n); }
+
 struct SolveWs {
     float2* B32;      // n x nrhs complex64 per matrix (ld n)
     double2* R;       // n x nrhs complex128 per matrix (ld n)
     void* Tm;         // SB x nrhs per matrix in the factor precision (group temp)
-    double* part;     // [batch][2][kNormBlocks]
+    float2* P;        // [batch][res_slice_count(n)] n x nrhs complex64: slices of Z D
+    double* bnd;      // [batch]: running error bound of the updated residual
+    double* part;     // [batch][kNormSlots][kNormBlocks]
     double* znorm;    // [batch]: ||Z||_F
     int32_t* active;  // [batch]
     harp_refine_report* rep;   // [batch]
@@ -1745,7 +1806,10 @@ size_t solve_ws_layout(int n, int nrhs, int batch, int dtype, int refine, SolveW
     W.B32 = reinterpret_cast<float2*>(take((dtype == HARP_C64) ? mat * batch * 8 : 0));
     W.R = reinterpret_cast<double2*>(take(refine ? mat * batch * 16 : 0));
     W.Tm = take(int64_t(kSB) * nrhs * batch * (dtype == HARP_C64 ? 8 : 16));
-    W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 2 * kNormBlocks * 8 : 0));
+    const bool upd = refine && dtype == HARP_C64;
+    W.P = reinterpret_cast<float2*>(take(upd ? int64_t(res_slice_count(n)) * mat * batch * 8 : 0));
+    W.bnd = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 8 : 0));
+    W.part = reinterpret_cast<double*>(take(refine ? int64_t(batch) * kNormSlots * kNormBlocks * 8 : 0));
     W.znorm = reinterpret_cast<double*>(take(refine ? int64_t(batch) * 8 : 0));
     W.active = reinterpret_cast<int32_t*>(take(refine ? int64_t(batch) * 4 : 0));
     W.rep = reinterpret_cast<harp_refine_report*>(take(refine ? int64_t(batch) * int64_t(sizeof(harp_refine_report)) : 0));
@@ -1912,38 +1976,105 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
     const unsigned gb = unsigned((batch + 63) / 64);
     const int rnblk = norm_blocks(n, nrhs);   // blocks per matrix of the residual and solution norms
     HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
-                     hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, batch));
+                     hipLaunchKernelGGL(refine_init_kernel, dim3(gb), dim3(64), 0, st, W.active, rep, W.bnd, batch));
     HARP_LAUNCH_CHECK();
     const bool z32 = refine->z_complex64 != 0;
     if ((s = fro_norms(refine->d_Z, z32, refine->ldz, refine->stride_z, n, n, batch, W.part, W.znorm, st)) !=
         HARP_OK)
         return s;
     int n_act = batch;   // systems the host knows to be active (work accounting of the timers only)
+    // error bound of a residual update R - Z D (complex64 Z and D, products
+    // accumulated in FP32 over at most Ks complex terms per slice, slices
+    // added in FP64): per element sqrt(2) gamma_{2 Ks + 2} (|Z| |D|), so in
+    // the Frobenius norm bc ||Z||_F ||D||_F, plus the FP64 rounding of X + D
+    // (u64 ||Z||_F ||X||_F) and terms flushed below the FP32 normal range
+    // (babs)
+    const int Ks = res_slice_k(n), n_sl = res_slice_count(n), full_sl = n / Ks, tail_k = n - full_sl * Ks;
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    const double m_terms = 2.0 * Ks + 2.0;
+    const double bc = 1.01 * std::sqrt(2.0) * m_terms * u32 / (1.0 - m_terms * u32);
+    const double babs = std::sqrt(2.0) * (2.0 * n + 2.0 * n_sl) * std::ldexp(1.0, -126) * std::sqrt(double(n) * nrhs);
+    const int dnblk = norm_blocks((n + 1) / 2, nrhs);
+    const bool dvec2 = n % 2 == 0 && (reinterpret_cast<uintptr_t>(W.B32) & 15) == 0;
     for (int it = 0;; ++it) {
-        // R = B - Z X  (FP64, MFMA)
-        GemmArgs<double> g;
-        g.M = n;
-        g.N = nrhs;
-        g.K = n;
-        // complex64 Z: widened to FP64 as the residual product loads it
-        g.A = z32 ? nullptr : static_cast<const double*>(refine->d_Z);
-        g.A32 = z32 ? static_cast<const float*>(refine->d_Z) : nullptr;
-        g.lda = refine->ldz;
-        g.sA = refine->stride_z;
-        g.B = static_cast<const double*>(d_X);
-        g.ldb = ldx;
-        g.sB = stride_x;
-        g.C = static_cast<const double*>(d_B);
-        g.ldc = ldb;
-        g.sC = stride_b;
-        g.D = reinterpret_cast<double*>(W.R);
-        g.ldd = n;
-        g.sD = mat;
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        g.active = W.active;
-        g.site = HARP_SITE_RESIDUAL;
-        if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
+        // the first residual after a correction is updated; any later one is
+        // a full FP64 residual again (which resets the bound), so a tolerance
+        // below the update's bound still converges, one sweep later
+        const bool update = it == 1 && z32 && W.P != nullptr;
+        if (!update) {
+            // R = B - Z X  (FP64, MFMA)
+            GemmArgs<double> g;
+            g.M = n;
+            g.N = nrhs;
+            g.K = n;
+            // complex64 Z: widened to FP64 as the residual product loads it
+            g.A = z32 ? nullptr : static_cast<const double*>(refine->d_Z);
+            g.A32 = z32 ? static_cast<const float*>(refine->d_Z) : nullptr;
+            g.lda = refine->ldz;
+            g.sA = refine->stride_z;
+            g.B = static_cast<const double*>(d_X);
+            g.ldb = ldx;
+            g.sB = stride_x;
+            g.C = static_cast<const double*>(d_B);
+            g.ldc = ldb;
+            g.sC = stride_b;
+            g.D = reinterpret_cast<double*>(W.R);
+            g.ldd = n;
+            g.sD = mat;
+            g.alpha = -1.0;
+            g.beta = 1.0;
+            g.active = W.active;
+            g.site = HARP_SITE_RESIDUAL;
+            if ((s = cgemm<double>(g, batch, st, n_act)) != HARP_OK) return s;
+        } else {
+            // R = R - Z D with D (W.B32) the complex64 correction the last
+            // sweep added to X: slice q of Z D (K range [q Ks, q Ks + Ks))
+            // into P[q], then the slices subtracted in FP64
+            GemmArgs<float> g{};
+            g.M = n;
+            g.N = nrhs;
+            g.K = Ks;
+            g.A = static_cast<const float*>(refine->d_Z);
+            g.lda = refine->ldz;
+            g.sA = refine->stride_z;
+            g.sA2 = int64_t(Ks) * refine->ldz;
+            g.B = reinterpret_cast<const float*>(W.B32);
+            g.ldb = n;
+            g.sB = mat;
+            g.sB2 = Ks;
+            g.C = nullptr;
+            g.D = reinterpret_cast<float*>(W.P);
+            g.ldd = n;
+            g.sD = int64_t(n_sl) * mat;
+            g.sD2 = mat;
+            g.alpha = 1.0f;
+            g.beta = 0.0f;
+            g.active = W.active;
+            g.site = HARP_SITE_RESIDUAL_UPDATE;
+            g.inner = full_sl;
+            if (full_sl > 0 && (s = cgemm<float>(g, batch, st, n_act)) != HARP_OK) return s;
+            if (tail_k > 0) {
+                g.inner = 1;
+                g.K = tail_k;
+                g.A += 2 * size_t(full_sl) * Ks * refine->ldz;
+                g.B += 2 * size_t(full_sl) * Ks;
+                g.D += 2 * size_t(full_sl) * mat;
+                g.sA2 = g.sB2 = g.sD2 = 0;
+                if ((s = cgemm<float>(g, batch, st, n_act)) != HARP_OK) return s;
+            }
+            const unsigned ub = unsigned(std::min<int64_t>((mat + 255) / 256, 2048));
+            HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                             hipLaunchKernelGGL(residual_update_kernel, dim3(ub, 1, batch), dim3(256), 0, st, W.R,
+                                                int64_t(n), mat, static_cast<const float2*>(W.P), mat,
+                                                int64_t(n_sl) * mat, n_sl, n, nrhs,
+                                                static_cast<const int32_t*>(W.active)));
+            HARP_LAUNCH_CHECK();
+            HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
+                             hipLaunchKernelGGL(sumsq_partial_c64_kernel, dim3(dnblk, 1, batch), dim3(256), 0, st,
+                                                static_cast<const float2*>(W.B32), int64_t(n), mat, n, nrhs, dvec2,
+                                                W.part, 2, static_cast<const int32_t*>(W.active)));
+            HARP_LAUNCH_CHECK();
+        }
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                          hipLaunchKernelGGL(sumsq_partial_kernel, dim3(rnblk, 2, batch), dim3(256), 0, st,
                                             static_cast<const double2*>(W.R), int64_t(n), mat,
@@ -1952,7 +2083,8 @@ harp_status solve_core(int32_t n, int32_t nrhs, int32_t batch, harp_dtype dtype,
         HARP_LAUNCH_CHECK();
         HARP_PROF_LAUNCH(HARP_K_AUX, st, 0.0, 0.0,
                          hipLaunchKernelGGL(refine_check_kernel, dim3(batch), dim3(256), 0, st, W.part, rnblk,
-                                            W.znorm, refine->tol, refine->max_iter, W.active, rep));
+                                            update ? dnblk : 0, W.znorm, refine->tol, refine->max_iter, bc,
+                                            babs, u64, W.bnd, W.active, rep));
         HARP_LAUNCH_CHECK();
         if (it == refine->max_iter) break;
         if (host && it >= 1) {

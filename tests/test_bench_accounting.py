@@ -55,6 +55,19 @@ def test_refinement_sweeps_scale_solves_and_residuals():
     assert plain["residuals"] == 0.0 and plain["solves"] == 2 * one["solves"]
 
 
+def test_residual_update_takes_the_first_check_after_a_correction():
+    # against a complex64 matrix the check after the first correction is a
+    # complex64 update; every other check stays an FP64 residual
+    n, nrhs = 100, 7
+    per = 8.0 * n * n * nrhs
+    w = bench.method_flops(n, nrhs, [0, 1, 3], residual_update=True)
+    assert w["residual_updates"] == 2 * per                 # the two systems that corrected
+    assert w["residuals"] == (1 + 1 + 3) * per              # checks 0, and 2..k
+    plain = bench.method_flops(n, nrhs, [0, 1, 3])
+    assert plain["residual_updates"] == 0.0 and plain["residuals"] == (1 + 2 + 4) * per
+    assert w["residuals"] + w["residual_updates"] == plain["residuals"]
+
+
 def _prof(**ms):
     classes = ("fill", "gemm_c64", "gemm_c128", "getf2", "trsm_lower", "trsm_upper", "rank_update")
     p = {k: {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0} for k in classes}
@@ -69,7 +82,11 @@ def test_attribution_conserves_the_method_flops():
                  rank_update={"ms": 0.5, "launches": 4, "flops": 1.0e6})
     steps, fill = 3, 5.0e8
     a = bench.attribute_method_flops(prof, steps, work, fill)
-    total = (work["lu"] + work["solves"] + work["residuals"] + fill) * steps
+    wu = bench.method_flops(256, 16, [1, 2], residual_update=True)
+    au = bench.attribute_method_flops(prof, steps, wu, fill)
+    assert math.isclose(sum(au.values()), sum(a.values()), rel_tol=1e-14)   # moved, not lost
+    assert math.isclose(au["gemm_c64"] - a["gemm_c64"], wu["residual_updates"] * steps, rel_tol=1e-12)
+    total = (work["lu"] + work["solves"] + work["residuals"] + work["residual_updates"] + fill) * steps
     assert math.isclose(sum(a.values()), total, rel_tol=1e-14)
     assert a["gemm_c128"] == work["residuals"] * steps
     # the plain path has no residual class; the FP64 GEMMs carry the LU

@@ -292,16 +292,21 @@ def test_refinement_report_and_noconv(api):
     assert rep[0]["converged"] and 1 <= rep[0]["iters"] <= 5 and rep[0]["resid_rel"] <= 1e-12
 
 
+@pytest.mark.parametrize("zdt", ["c128", "c64"])
 @pytest.mark.parametrize("max_iter", [0, 1, 4])
-def test_refinement_device_control_matches_host(api, max_iter):
+def test_refinement_device_control_matches_host(api, max_iter, zdt):
     """The refinement without a host report (nothing synchronises; every
     sweep of the budget is enqueued and converged systems skip it) gives the
     same solution and the same per-system report as with one, bit for bit,
     over a batch whose systems need different numbers of corrections (one
-    system never converges within the budget)."""
+    system never converges within the budget); against a complex128 matrix
+    and against a complex64 one (whose first check after a correction is the
+    complex64 residual update)."""
     n = 130
     A = _rand((3, n, n), 18) + np.array([3.0, 0.5, 3.0])[:, None, None] * np.sqrt(n) * np.eye(n)[None]
-    Z64 = _to_cm(api, A, torch.complex128)
+    if zdt == "c64":
+        A = A.astype(np.complex64).astype(np.complex128)
+    Z64 = _to_cm(api, A, torch.complex128) if zdt == "c128" else _to_cm(api, A.astype(np.complex64), torch.complex64)
     F = api.reduced_factor(_to_cm(api, A.astype(np.complex64), torch.complex64))
     B = _to_cm(api, _rand((3, n, 5), 19), torch.complex128)
     tols = 1e-13
@@ -317,6 +322,43 @@ def test_refinement_device_control_matches_host(api, max_iter):
         assert all(r["converged"] for r in rh)
         ref = np.linalg.solve(A, B.cpu().numpy())
         assert np.linalg.norm(Xd.cpu().numpy() - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("n,nrhs", [(300, 9), (1100, 19), (2048, 64)])
+def test_updated_residual_within_its_bound(api, n, nrhs):
+    """Against a complex64 matrix, the check after the first correction
+    updates the residual, R1 = R0 - Z D, with complex64 products summed over
+    K slices in FP64, and accepts only when |R1| plus its error bound meets
+    the tolerance.  The correction D is X1 - X0 (max_iter 0 and 1 give X0 and
+    X1; the kernels are deterministic), so the host can recompute the true
+    FP64 residual of X1 and the bound sqrt(2) gamma_{2 Ks + 2} |Z| |D| (Ks the
+    slice length, at most 256 here): the reported residual is within the
+    bound of the true one, and the true one within the tolerance."""
+    # well conditioned (diagonal 8 sqrt(n) against a spectral radius of about
+    # sqrt(2 n)), so that one correction is small enough to be certified by
+    # the update (a poorly conditioned system would take a second, FP64 check)
+    A = (_rand((1, n, n), 90 + n) + 8 * np.sqrt(n) * np.eye(n)[None]).astype(np.complex64)
+    Bh = _rand((1, n, nrhs), 91 + n)
+    Zc = _to_cm(api, A, torch.complex64)
+    F = api.reduced_factor(_to_cm(api, A, torch.complex64))
+    B = _to_cm(api, Bh, torch.complex128)
+    X0, r0 = api.reduced_solve(F, B, Z64=Zc, tol=0.0, max_iter=0, raise_noconv=False)
+    X1, r1 = api.reduced_solve(F, B, Z64=Zc, tol=1e-10, max_iter=1)
+    torch.cuda.synchronize()
+    assert r1[0]["iters"] == 1 and r1[0]["converged"], r1
+    A64 = A[0].astype(np.complex128)
+    x0, x1 = X0.cpu().numpy()[0], X1.cpu().numpy()[0]
+    d = x1 - x0
+    zn, xn = np.linalg.norm(A64), np.linalg.norm(x1)
+    true = np.linalg.norm(Bh[0] - A64 @ x1)
+    reported = r1[0]["resid_rel"] * zn * xn
+    ks = (((n + min(8, max(1, (n + 255) // 256)) - 1) // min(8, max(1, (n + 255) // 256))) + 15) // 16 * 16
+    m = 2 * ks + 2
+    bound = 1.01 * np.sqrt(2) * m * 2.0**-24 / (1 - m * 2.0**-24) * zn * np.linalg.norm(d) + 2.0**-53 * zn * xn
+    # the host's own FP64 product rounds too: a margin of n u64 |Z| |X|
+    slack = n * 2.0**-53 * zn * xn
+    assert abs(reported - true) <= bound + slack, (reported, true, bound)
+    assert true <= 1e-10 * zn * xn
 
 
 def _pipeline(api, models_o, x, y, refined=True, keep_z=False):
