@@ -314,7 +314,7 @@ typedef struct {
                             factors too, the check after the first
                             correction D (complex64, added to X in FP64)
                             updates the residual instead, R - Z D, with
-                            complex64 products over at most 8 K slices
+                            complex64 products over at most 16 K slices
                             added in FP64; it counts as converged only when
                             ||R||_F plus the update's error bound
                             (sqrt(2) gamma_{2 Ks + 2} ||Z||_F ||D||_F, Ks

@@ -1772,7 +1772,7 @@ harp_status fro_norms(const void* M, bool complex64, int64_t ld, int64_t s, int 
 // (the last one shorter), each on the FP32 matrix cores, the slices added in
 // FP64.  Each slice's products are accumulated in FP32 over at most
 // res_slice_k(n) complex terms, which bounds their error (residual_bound).
-constexpr int kResSlicesMax = 8;
+constexpr int kResSlicesMax = 16;
 inline int res_slices(int n) { return std::max(1, std::min(kResSlicesMax, (n + 255) / 256)); }
 inline int res_slice_k(int n) {
     const int S = res_slices(n), ks = (n + S - 1) / S;

@@ -352,7 +352,8 @@ def test_updated_residual_within_its_bound(api, n, nrhs):
     zn, xn = np.linalg.norm(A64), np.linalg.norm(x1)
     true = np.linalg.norm(Bh[0] - A64 @ x1)
     reported = r1[0]["resid_rel"] * zn * xn
-    ks = (((n + min(8, max(1, (n + 255) // 256)) - 1) // min(8, max(1, (n + 255) // 256))) + 15) // 16 * 16
+    n_sl = min(16, max(1, (n + 255) // 256))
+    ks = ((n + n_sl - 1) // n_sl + 15) // 16 * 16
     m = 2 * ks + 2
     bound = 1.01 * np.sqrt(2) * m * 2.0**-24 / (1 - m * 2.0**-24) * zn * np.linalg.norm(d) + 2.0**-53 * zn * xn
     # the host's own FP64 product rounds too: a margin of n u64 |Z| |X|
