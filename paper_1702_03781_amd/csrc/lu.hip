@@ -492,6 +492,29 @@ __device__ void block_finish(const PanelArgs& pa, int b, int tid, BlkShared<T>& 
 // multipliers times U, and the second block is factored like the first.
 // One launch then covers 2 W columns, and the outer block's remaining columns
 // take one update per 2 W columns.
+// true when a panel of RPT rows x W complex values per thread fits the VGPR
+// budget of an NT-thread workgroup (512 / (NT / 256) per lane, minus headroom)
+template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
+    return RPT * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
+}
+// widest register block (8, 4, 2 or 1 columns) that RPT rows per thread hold
+// within the budget of 1024 threads
+template <typename T, int RPT> constexpr int panel_block_w() {
+    return panel_fits_r<T, 1024, RPT, 8>() ? 8
+           : panel_fits_r<T, 1024, RPT, 4>() ? 4
+           : panel_fits_r<T, 1024, RPT, 2>() ? 2 : 1;
+}
+// A panel of W columns at RPT rows per thread: H = 1 or 2 register blocks of
+// WB columns.  When the two blocks do not fit in registers together, the
+// first is written back and re-read from memory for the second block's
+// update (single precision only).
+template <typename T, int W, int RPT> struct PanelSplit {
+    static constexpr int WB = W < panel_block_w<T, RPT>() ? W : panel_block_w<T, RPT>();
+    static constexpr int H = W / WB;
+    static constexpr bool ok =
+        WB * H == W && H <= 2 && (H == 1 || panel_fits_r<T, 1024, RPT, W>() || sizeof(T) == 4);
+};
+
 template <typename T, int NT, int RPT, int W, int H>
 __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     using V = typename C2<T>::t;
@@ -500,6 +523,14 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
     static_assert(NW <= 16, "candidates are reduced within one 16-lane row");
     static_assert(H == 1 || H == 2, "one or two register blocks");
     static_assert(2 * WT + 2 * W <= NT, "one thread per row of the exchange maps");
+    // the two blocks do not fit in registers together: the first block's
+    // multipliers are re-read from memory (where this thread wrote them) for
+    // the second block's update
+    constexpr bool RELOAD = H == 2 && !panel_fits_r<T, NT, RPT, WT>();
+    // column k + 1 of the re-read multipliers is loaded while column k is
+    // applied, except at 8 rows per thread (the registers are full there;
+    // measured the same either way)
+    constexpr bool PREFETCH = RPT <= 4;
     const int b = blockIdx.x;
     V* A = reinterpret_cast<V*>(pa.A) + size_t(b) * pa.sA;
     const int64_t lda = pa.lda;
@@ -599,20 +630,53 @@ __global__ void __launch_bounds__(NT) getf2_kernel(PanelArgs pa) {
             __syncthreads();
             // rows below the first block: a2 -= L U, one row of U at a time
             // (the compiler fence keeps all 64 entries of U from being loaded
-            // into registers at once); the top rows of a2 become U
+            // into registers at once); the top rows of a2 become U.  With
+            // RELOAD, column k of L comes from memory.
+            if constexpr (RELOAD) {
+                V lk[RPT], ln[RPT];
+                auto load_l = [&](int k, V (&l)[RPT]) {
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                V u[W];
+                    for (int r = 0; r < RPT; ++r)
+                        l[r] = (lrow[r] >= j0 + W && lrow[r] < n) ? A[size_t(j0 + k) * lda + lrow[r]]
+                                                                    : V{T(0), T(0)};
+                };
+                load_l(0, lk);
 #pragma unroll
-                for (int c = 0; c < W; ++c) u[c] = sh.Ub[k][c];
+                for (int k = 0; k < W; ++k) {
+                    if (PREFETCH && k + 1 < W) load_l(k + 1, ln);
+                    V u[W];
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) {
-                    if (lrow[r] >= j0 + W) {
+                    for (int c = 0; c < W; ++c) u[c] = sh.Ub[k][c];
 #pragma unroll
-                        for (int c = 0; c < W; ++c) a2[r][c] = cfms(a2[r][c], a[r][k], u[c]);
+                    for (int r = 0; r < RPT; ++r) {
+                        if (lrow[r] >= j0 + W) {
+#pragma unroll
+                            for (int c = 0; c < W; ++c) a2[r][c] = cfms(a2[r][c], lk[r], u[c]);
+                        }
                     }
+                    if constexpr (PREFETCH) {
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) lk[r] = ln[r];
+                    } else if (k + 1 < W) {
+                        load_l(k + 1, lk);
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
                 }
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            } else {
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    V u[W];
+#pragma unroll
+                    for (int c = 0; c < W; ++c) u[c] = sh.Ub[k][c];
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        if (lrow[r] >= j0 + W) {
+#pragma unroll
+                            for (int c = 0; c < W; ++c) a2[r][c] = cfms(a2[r][c], a[r][k], u[c]);
+                        }
+                    }
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                }
             }
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -1316,32 +1380,25 @@ template <typename T> struct LuCfg {
     static constexpr int NS = 4;    // outer blocks per trailing update (its contraction is NS * NB)
 };
 
-// Panel width: the register-resident panel holds RPT x W complex values per
-// thread with 1024 threads (64 VGPRs of budget per lane for the panel); W
-// shrinks as the matrix grows so the panel stays in registers.  Single
-// precision up to 2048 rows: 16 columns as two register blocks of 8.  These
-// are the defaults of the tuning table (harp_set_tuning), which can choose
-// another feasible width and the GEMM tile switch per order.
+// Panel width: the register-resident panel holds RPT x WB complex values per
+// thread in each of its one or two register blocks with 1024 threads (64
+// VGPRs of budget per lane for a block).  Single precision: 16 columns (two
+// blocks of 8) up to 4096 rows, 8 columns (two blocks of 4) up to 8192 rows;
+// above 2048 rows the first block is re-read from memory for the second's
+// update.  These are the defaults of the tuning table (harp_set_tuning),
+// which can choose another feasible width and the GEMM tile switch per order.
 template <typename T> inline int default_panel_width(int n) {
-    if (sizeof(T) == 4) return n <= 2048 ? 16 : (n <= 4096 ? 8 : 4);
+    if (sizeof(T) == 4) return n <= 4096 ? 16 : 8;
     return n <= 2048 ? 8 : (n <= 4096 ? 4 : 2);
 }
 
 
-// true when a panel of RPT rows x W complex values per thread fits the VGPR
-// budget of an NT-thread workgroup (512 / (NT / 256) per lane, minus headroom)
-template <typename T, int NT, int RPT, int W> constexpr bool panel_fits_r() {
-    return RPT * W * 2 * int(sizeof(T) / 4) <= (512 / (NT / 256)) - 64;
-}
-
 // true when a panel of width W has a launch configuration for every height up
 // to n rows (the selection of launch_getf2_w)
 template <typename T, int W> constexpr bool panel_feasible_w(int n) {
-    constexpr int WB = W > 8 ? 8 : W, H = W / WB;
-    if (n <= 1024 * 2) return panel_fits_r<T, 1024, 2, WB * H>();
-    if (H != 1) return false;
-    if (n <= 1024 * 4) return panel_fits_r<T, 1024, 4, WB>();
-    if (n <= 1024 * 8) return panel_fits_r<T, 1024, 8, WB>();
+    if (n <= 1024 * 2) return PanelSplit<T, W, 2>::ok;
+    if (n <= 1024 * 4) return PanelSplit<T, W, 2>::ok && PanelSplit<T, W, 4>::ok;
+    if (n <= 1024 * 8) return PanelSplit<T, W, 2>::ok && PanelSplit<T, W, 4>::ok && PanelSplit<T, W, 8>::ok;
     return false;
 }
 template <typename T> bool panel_feasible(int W, int n) {
@@ -1376,7 +1433,7 @@ template <typename T> Tune tuning_for(int n) {
 // H register blocks of W columns
 template <typename T, int NT, int RPT, int W, int H>
 harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
-    if constexpr (panel_fits_r<T, NT, RPT, W * H>()) {
+    if constexpr (panel_fits_r<T, NT, RPT, W>() && (H == 1 || panel_fits_r<T, NT, RPT, W * H>() || sizeof(T) == 4)) {
         // algorithmic work: the panel's own elimination (rank-1 updates of
         // m rows x w columns) and the unit-lower solve of the w top rows of
         // the outer block's columns to its right
@@ -1394,20 +1451,30 @@ harp_status launch_getf2_cfg(const PanelArgs& pa, int batch, hipStream_t st) {
 
 // Two rows per thread while the panel is at most 2048 rows high (the
 // workgroup shrinks with the panel: fewer waves share the per-column
-// reductions), then more rows per thread with 1024 threads.  A 16-column
-// panel is two blocks of 8 and needs two rows per thread.
+// reductions), then 4 or 8 rows per thread with 1024 threads; each height
+// range takes its own split of the W columns into register blocks.
 template <typename T, int W>
 harp_status launch_getf2_w(const PanelArgs& pa, int batch, hipStream_t st) {
     const int m = pa.n - pa.j0;
     if (pa.w > W) return HARP_E_ARG;
-    constexpr int WB = W > 8 ? 8 : W, H = W / WB;
-    static_assert(WB * H == W && H <= 2, "panel width");
-    if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, WB, H>(pa, batch, st);
-    if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, WB, H>(pa, batch, st);
-    if (m <= 1024 * 2) return launch_getf2_cfg<T, 1024, 2, WB, H>(pa, batch, st);
-    if constexpr (H == 1) {
-        if (m <= 1024 * 4) return launch_getf2_cfg<T, 1024, 4, WB, H>(pa, batch, st);
-        if (m <= 1024 * 8) return launch_getf2_cfg<T, 1024, 8, WB, H>(pa, batch, st);
+    using S2 = PanelSplit<T, W, 2>;
+    using S4 = PanelSplit<T, W, 4>;
+    using S8 = PanelSplit<T, W, 8>;
+    if (m <= 1024 * 2) {
+        if constexpr (S2::ok) {
+            if (m <= 256 * 2) return launch_getf2_cfg<T, 256, 2, S2::WB, S2::H>(pa, batch, st);
+            if (m <= 512 * 2) return launch_getf2_cfg<T, 512, 2, S2::WB, S2::H>(pa, batch, st);
+            return launch_getf2_cfg<T, 1024, 2, S2::WB, S2::H>(pa, batch, st);
+        }
+        return HARP_E_ARG;
+    }
+    if (m <= 1024 * 4) {
+        if constexpr (S4::ok) return launch_getf2_cfg<T, 1024, 4, S4::WB, S4::H>(pa, batch, st);
+        return HARP_E_ARG;
+    }
+    if (m <= 1024 * 8) {
+        if constexpr (S8::ok) return launch_getf2_cfg<T, 1024, 8, S8::WB, S8::H>(pa, batch, st);
+        return HARP_E_ARG;
     }
     return HARP_E_ARG;
 }

@@ -127,7 +127,11 @@ def test_tuning_table_validation(L):
     assert L.harp_get_tuning(out, 8, ctypes.byref(n)) == 0 and n.value == 3
     assert [(e.max_order, e.panel_width_c64, e.panel_width_c128, e.small_grid_wgs) for e in out[:3]] == \
         [(1024, 8, 4, 256), (2048, 16, 8, 1024), (8192, 4, 2, 4096)]
-    assert put([(4096, 16, 4, 1024)]) == -1          # two register blocks need at most 2048 rows
+    # complex64: 16 columns (two blocks of 8) up to 4096 rows, the first block
+    # re-read from memory above 2048; 8192 rows would need four blocks of 4
+    assert put([(4096, 16, 4, 1024)]) == 0
+    assert put([(8192, 16, 2, 1024)]) == -1
+    assert put([(8192, 8, 2, 1024)]) == 0           # two blocks of 4 at 8 rows per thread
     assert put([(4096, 8, 8, 1024)]) == -1           # complex128 width 8 has no configuration past 2048 rows
     assert put([(2048, 8, 4, 1024), (1024, 8, 4, 1024)]) == -1   # not ascending
     assert put([(2048, 3, 4, 1024)]) == -1
@@ -135,4 +139,5 @@ def test_tuning_table_validation(L):
     assert L.harp_get_tuning(out, 8, ctypes.byref(n)) == 0 and n.value == 0
     d = HarpTuningEntry()
     assert L.harp_default_tuning(2048, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (16, 8)
-    assert L.harp_default_tuning(8192, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (4, 2)
+    assert L.harp_default_tuning(4096, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (16, 4)
+    assert L.harp_default_tuning(8192, ctypes.byref(d)) == 0 and (d.panel_width_c64, d.panel_width_c128) == (8, 2)
