@@ -180,6 +180,30 @@ def test_sparse_right_hand_sides_with_row_exchanges(api, dtype):
             assert err <= tol, (b, c, err)
 
 
+@pytest.mark.parametrize("n", [3000, 5000])
+def test_tall_complex64_panels_pivot_and_solve(api, n):
+    """Complex64 panels taller than 2048 rows keep two register blocks (16
+    columns at 4 rows per thread up to 4096 rows, 8 at 8 rows per thread
+    above), the first block re-read from memory for the second's update.  A
+    row-permuted, strongly diagonally dominant matrix makes partial pivoting
+    unambiguous in any precision: the pivots must undo the permutation
+    exactly, and the complex64 solve agrees with LAPACK."""
+    rng = np.random.default_rng(700 + n)
+    D = 0.1 * _rand((n, n), 701 + n) + 10.0 * n * np.exp(1j * rng.uniform(0, 2 * np.pi, n)) * np.eye(n)
+    p0 = rng.permutation(n)
+    A = D[p0][None].astype(np.complex64)             # row i of A is row p0[i] of D
+    F = api.reduced_factor(_to_cm(api, A, torch.complex64))
+    Bh = _rand((1, n, 7), 702 + n)
+    X, _ = api.reduced_solve(F, _to_cm(api, Bh, torch.complex128))
+    torch.cuda.synchronize()
+    perm = np.arange(n)
+    for i, q in enumerate(F.ipiv.cpu().numpy()[0]):
+        perm[i], perm[q] = perm[q], perm[i]
+    assert np.array_equal(p0[perm], np.arange(n))   # position j holds D's row j
+    ref = np.linalg.solve(A[0].astype(np.complex128), Bh[0])
+    assert np.linalg.norm(X.cpu().numpy()[0] - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
 def test_pivots_follow_partial_pivoting(api):
     """Generic matrix: the pivot sequence is LAPACK's (first max |Re|+|Im|)."""
     import scipy.linalg
